@@ -1,0 +1,640 @@
+/*
+ * Plain FP64 CPU oracle of the adaptive D2Q21 compressible LBM
+ * (Coreixas & Latt, arXiv 2009.13426).  TEST INFRASTRUCTURE ONLY: see
+ * lbm_oracle.h.  Each function follows the passage of the paper cited above
+ * it; readings of passages the paper leaves open are marked "Reading".
+ *
+ * No blocking, fusion or reordering beyond what the paper's algorithm states:
+ * one time iteration is, in order (Sec. IV.A.4, "Algorithm overview"),
+ *   streaming in pull form with Grad reconstruction of populations whose
+ *   source node lives in another lattice (eqs. stream, GradGeneral),
+ *   macroscopic moments (eq. polyTemp),
+ *   lattice selection from the local velocity (eq. criterion),
+ *   numerical equilibrium f_eq (eq. feqNum_8Mom), g_eq (eq. gEq),
+ *   BGK collision (eq. coll).
+ * Storing post-collision populations makes "streaming" the first pass of each
+ * call; the cycle is the paper's.
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- lattice
+ * D2Q21 (Sec. I, Fig. 1; lattice of Zhang et al.).  The velocity table is not
+ * printed in the paper.  Reading: the rest velocity, (+-1,0) and (0,+-1),
+ * (+-1,+-1), (+-2,0) and (0,+-2), (+-2,+-2), (+-3,0) and (0,+-3).  This set
+ * is symmetric under the square's symmetry group and contains the reference
+ * populations (0,0), (-1,0), (1,1) named in the caption of Fig. 1. */
+static const int XI[ORC_Q][2] = {
+    {0, 0},
+    {1, 0},  {-1, 0},  {0, 1},  {0, -1},
+    {1, 1},  {-1, 1},  {-1, -1}, {1, -1},
+    {2, 0},  {-2, 0},  {0, 2},  {0, -2},
+    {2, 2},  {-2, 2},  {-2, -2}, {2, -2},
+    {3, 0},  {-3, 0},  {0, 3},  {0, -3}};
+
+void orc_velocities(int* cx, int* cy) {
+  for (int i = 0; i < ORC_Q; ++i) {
+    cx[i] = XI[i][0];
+    cy[i] = XI[i][1];
+  }
+}
+
+/* ------------------------------------------------ numerical equilibrium
+ * Eq. (feqNum_8Mom): f_i^eq = rho exp[-(1 + lambda . phi(xi_i))] with the
+ * monomials of the 8-moment set, eq. (8moments):
+ *   phi = (1, xi_x, xi_y, xi_x^2, xi_x xi_y, xi_y^2, xi_x |xi|^2, xi_y |xi|^2).
+ * Reading: the constraints are written in the frame of the lattice, i.e.
+ * with the integer-valued xi_i and the peculiar velocity u - U; the span of
+ * phi is invariant under integer translations, so this is the same
+ * equilibrium as the one written with c_i = xi_i + U and u. */
+static void basis(int i, double phi[ORC_M]) {
+  double x = XI[i][0], y = XI[i][1];
+  double s = x * x + y * y;
+  phi[0] = 1.0;
+  phi[1] = x;
+  phi[2] = y;
+  phi[3] = x * x;
+  phi[4] = x * y;
+  phi[5] = y * y;
+  phi[6] = x * s;
+  phi[7] = y * s;
+}
+
+/* Constraint targets per unit density, eqs. (G0_8mom)-(G3yaa_8mom), with the
+ * energy 2E = u_x^2 + u_y^2 + D T (App. C, D = 2). */
+void orc_targets(double ux, double uy, double T, double* m) {
+  double E = 0.5 * (ux * ux + uy * uy + ORC_D * T);
+  m[0] = 1.0;
+  m[1] = ux;
+  m[2] = uy;
+  m[3] = ux * ux + T;
+  m[4] = ux * uy;
+  m[5] = uy * uy + T;
+  m[6] = 2.0 * ux * (E + T);
+  m[7] = 2.0 * uy * (E + T);
+}
+
+/* Weights w_i = exp(-(1 + lambda.phi_i)), constraint residuals
+ * G_a = sum_i w_i phi_a(xi_i) - m_a (eq. constraints) and the value of the
+ * convex dual Psi(lambda) = sum_i w_i + lambda.m, whose gradient is -G and
+ * whose Hessian is H = sum_i w_i phi phi^T (positive definite since phi has
+ * rank 8 on the lattice).  Minimising Psi is the entropy problem of
+ * eqs. (Hfunction)-(exponential) with prefactor a = rho. */
+static double evaluate(const double lam[ORC_M], const double m[ORC_M],
+                       double w[ORC_Q], double G[ORC_M]) {
+  double phi[ORC_M];
+  double psi = 0.0;
+  for (int a = 0; a < ORC_M; ++a) G[a] = -m[a];
+  for (int i = 0; i < ORC_Q; ++i) {
+    basis(i, phi);
+    double e = 1.0;
+    for (int a = 0; a < ORC_M; ++a) e += lam[a] * phi[a];
+    w[i] = exp(-e);
+    for (int a = 0; a < ORC_M; ++a) G[a] += w[i] * phi[a];
+    psi += w[i];
+  }
+  for (int a = 0; a < ORC_M; ++a) psi += lam[a] * m[a];
+  return psi;
+}
+
+static void hessian(const double w[ORC_Q], double H[ORC_M][ORC_M]) {
+  double phi[ORC_M];
+  memset(H, 0, sizeof(double) * ORC_M * ORC_M);
+  for (int i = 0; i < ORC_Q; ++i) {
+    basis(i, phi);
+    for (int a = 0; a < ORC_M; ++a)
+      for (int b = 0; b < ORC_M; ++b) H[a][b] += w[i] * phi[a] * phi[b];
+  }
+}
+
+/* Gaussian elimination with partial pivoting for H d = G. */
+static int solve(double Hin[ORC_M][ORC_M], const double G[ORC_M], double d[ORC_M]) {
+  double A[ORC_M][ORC_M + 1];
+  for (int r = 0; r < ORC_M; ++r) {
+    for (int c = 0; c < ORC_M; ++c) A[r][c] = Hin[r][c];
+    A[r][ORC_M] = G[r];
+  }
+  for (int c = 0; c < ORC_M; ++c) {
+    int p = c;
+    for (int r = c + 1; r < ORC_M; ++r)
+      if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+    if (!(fabs(A[p][c]) > 0.0)) return -1;
+    if (p != c)
+      for (int k = 0; k <= ORC_M; ++k) {
+        double t = A[c][k];
+        A[c][k] = A[p][k];
+        A[p][k] = t;
+      }
+    for (int r = c + 1; r < ORC_M; ++r) {
+      double f = A[r][c] / A[c][c];
+      for (int k = c; k <= ORC_M; ++k) A[r][k] -= f * A[c][k];
+    }
+  }
+  for (int r = ORC_M - 1; r >= 0; --r) {
+    double acc = A[r][ORC_M];
+    for (int k = r + 1; k < ORC_M; ++k) acc -= A[r][k] * d[k];
+    d[r] = acc / A[r][r];
+  }
+  return 0;
+}
+
+static double maxabs(const double* v, int n) {
+  double r = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double a = fabs(v[k]);
+    if (!(a <= r)) r = a; /* propagates NaN */
+  }
+  return r;
+}
+
+/* Initial guess: the lattice-normalised Maxwellian, lambda_1 = -u/T,
+ * lambda_2 = I / (2T), cross and third-order multipliers zero, lambda_0
+ * such that sum_i w_i = 1. */
+static void maxwellian_guess(double ux, double uy, double T, double lam[ORC_M]) {
+  double phi[ORC_M];
+  for (int a = 0; a < ORC_M; ++a) lam[a] = 0.0;
+  lam[1] = -ux / T;
+  lam[2] = -uy / T;
+  lam[3] = 0.5 / T;
+  lam[5] = 0.5 / T;
+  double z = 0.0;
+  for (int i = 0; i < ORC_Q; ++i) {
+    basis(i, phi);
+    double e = 0.0;
+    for (int a = 1; a < ORC_M; ++a) e += lam[a] * phi[a];
+    z += exp(-e);
+  }
+  lam[0] = log(z) - 1.0;
+}
+
+/* Root finding for the multipliers (App. C; the paper uses a globalised
+ * Newton method with a 1e-12 criterion).  Newton steps d = H^{-1} G on the
+ * convex dual, globalised by backtracking on Psi (a full step is also
+ * accepted when it halves the residual, since near the root the change of Psi
+ * falls below its rounding).  Stop when max_a |G_a| <= tol, then apply one
+ * more plain Newton step so that the constraints hold to rounding.
+ * Reading: the polishing step. */
+int orc_equilibrium(double ux, double uy, double T, const double* lam0,
+                    double tol, int max_iter, double* w, double* lam, int* iters) {
+  double m[ORC_M], l[ORC_M], G[ORC_M], d[ORC_M], H[ORC_M][ORC_M];
+  double wt[ORC_Q], lt[ORC_M], Gt[ORC_M];
+  if (iters) *iters = 0;
+  if (!(T > 0.0) || !isfinite(T) || !isfinite(ux) || !isfinite(uy))
+    return ORC_ERR_NONPHYSICAL;
+  orc_targets(ux, uy, T, m);
+  if (lam0)
+    memcpy(l, lam0, sizeof l);
+  else
+    maxwellian_guess(ux, uy, T, l);
+  double psi = evaluate(l, m, w, G);
+  for (int it = 0; it < max_iter; ++it) {
+    double r = maxabs(G, ORC_M);
+    if (!isfinite(r) || !isfinite(psi)) return ORC_ERR_NEWTON;
+    hessian(w, H);
+    if (solve(H, G, d)) return ORC_ERR_NEWTON;
+    if (r <= tol) { /* converged: one polishing Newton step */
+      for (int a = 0; a < ORC_M; ++a) l[a] += d[a];
+      evaluate(l, m, w, G);
+      if (!isfinite(maxabs(G, ORC_M))) return ORC_ERR_NEWTON;
+      memcpy(lam, l, sizeof l);
+      if (iters) *iters = it + 1;
+      return ORC_OK;
+    }
+    double slope = 0.0; /* directional derivative of Psi along d: -G.d < 0 */
+    for (int a = 0; a < ORC_M; ++a) slope -= G[a] * d[a];
+    double t = 1.0, psit;
+    for (;;) {
+      for (int a = 0; a < ORC_M; ++a) lt[a] = l[a] + t * d[a];
+      psit = evaluate(lt, m, wt, Gt);
+      if (isfinite(psit)) {
+        if (psit <= psi + 1e-4 * t * slope) break;
+        if (t == 1.0 && maxabs(Gt, ORC_M) < 0.5 * r) break;
+      }
+      t *= 0.5;
+      if (t < 1e-12) return ORC_ERR_NEWTON;
+    }
+    memcpy(l, lt, sizeof l);
+    memcpy(w, wt, sizeof wt);
+    memcpy(G, Gt, sizeof Gt);
+    psi = psit;
+  }
+  return ORC_ERR_NEWTON;
+}
+
+/* ------------------------------------------------------ Grad populations
+ * Eqs. (GradGeneral), (GradGeneral_f), (GradGeneral_g):
+ *   h ~ h_eq (1 + phi_h),
+ *   phi_f = sigma:cbar cbar / (2 rho T^2)
+ *           + q.cbar / (rho Cp T^2) (|cbar|^2 / (2T) - Cp),
+ *   phi_g = 2 q.cbar / (rho Cp)            (Reading: as printed),
+ *   -sigma = mu [grad u + grad u^T - (2/D) div u I],  mu = rho nu,
+ *   q = -kappa grad T,  cbar = c_i - u,  c_i = xi_i + U.
+ * Reading: kappa = rho Cp nu (unit Prandtl number of BGK, Sec. IV.A.1),
+ * Cp = gamma / (gamma - 1).  Post-collision populations follow from
+ * h* = h_eq + (1 - 1/tau) h_neq with h_neq = h_eq phi_h (Sec. III.B.2),
+ * tau = 1/2 + nu / T (App. E). */
+#define ORC_GRAD_G_COEFF 2.0
+
+static void grad_phi(const orc_params* p, int i, double rho, double ux, double uy,
+                     double T, const double* du, const double* dT, int Lx, int Ly,
+                     double* phif, double* phig) {
+  double Cv = 1.0 / (p->gamma - 1.0), Cp = p->gamma * Cv;
+  double cbx = (double)(XI[i][0] + Lx) - ux;
+  double cby = (double)(XI[i][1] + Ly) - uy;
+  double mu = rho * p->nu;
+  double div = du[0] + du[3];
+  double sxx = -mu * (2.0 * du[0] - (2.0 / ORC_D) * div);
+  double syy = -mu * (2.0 * du[3] - (2.0 / ORC_D) * div);
+  double sxy = -mu * (du[1] + du[2]);
+  double kappa = rho * Cp * p->nu;
+  double qx = -kappa * dT[0], qy = -kappa * dT[1];
+  double qc = qx * cbx + qy * cby;
+  double c2 = cbx * cbx + cby * cby;
+  *phif = (sxx * cbx * cbx + 2.0 * sxy * cbx * cby + syy * cby * cby) / (2.0 * rho * T * T) +
+          qc / (rho * Cp * T * T) * (c2 / (2.0 * T) - Cp);
+  *phig = ORC_GRAD_G_COEFF * qc / (rho * Cp);
+}
+
+int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
+                         double T, const double* du, const double* dT, int Lx,
+                         int Ly, int post, double* f, double* g) {
+  double w[ORC_Q], lam[ORC_M];
+  double Cv = 1.0 / (p->gamma - 1.0);
+  if (!(rho > 0.0) || !isfinite(rho)) return ORC_ERR_NONPHYSICAL;
+  int rc = orc_equilibrium(ux - Lx, uy - Ly, T, NULL, p->newton_tol,
+                           p->newton_max_iter, w, lam, NULL);
+  if (rc) return rc;
+  double tau = 0.5 + p->nu / T;
+  double k = post ? (1.0 - 1.0 / tau) : 1.0;
+  for (int i = 0; i < ORC_Q; ++i) {
+    double phif, phig;
+    grad_phi(p, i, rho, ux, uy, T, du, dT, Lx, Ly, &phif, &phig);
+    double feq = rho * w[i];
+    double geq = (2.0 * Cv - ORC_D) * T * feq; /* eq. (gEq) */
+    f[i] = feq * (1.0 + k * phif);
+    g[i] = geq * (1.0 + k * phig);
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------ simulation */
+struct orc_sim {
+  orc_params p;
+  long N;
+  double *f, *g;         /* post-collision populations at time t */
+  double *fp, *gp;       /* streamed (pre-collision) populations at t+1 */
+  double *mac, *mac1;    /* rho, ux, uy, T per node */
+  int *Uc, *Un, *Uc1, *Un1;
+  int* Us;               /* static per-node shifts (shift_mode 2) */
+  orc_stats st;
+};
+
+static long wrap(long v, long n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+/* Eq. (criterion): n - 1/2 < u <= n + 1/2  <=>  U = n, i.e. U = ceil(u - 1/2).
+ * Reading of the overlapping-range remark (Sec. III.A.2): with a half-width
+ * w > 1/2 the previous shift is kept while U_prev - w < u <= U_prev + w. */
+static int select_axis(double u, int Uprev, double w) {
+  if (u > Uprev - w && u <= Uprev + w) return Uprev;
+  return (int)ceil(u - 0.5);
+}
+
+int orc_select(double u, int Uprev, double halfwidth) {
+  return select_axis(u, Uprev, halfwidth);
+}
+
+orc_sim* orc_create(const orc_params* p) {
+  if (!p || p->nx < 1 || p->ny < 1 || !(p->gamma > 1.0) || !(p->nu >= 0.0) ||
+      p->newton_max_iter < 1 || !(p->halfwidth >= 0.5))
+    return NULL;
+  orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
+  if (!s) return NULL;
+  s->p = *p;
+  s->N = (long)p->nx * p->ny;
+  long N = s->N;
+  s->f = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
+  s->g = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
+  s->fp = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
+  s->gp = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
+  s->mac = (double*)calloc((size_t)4 * N, sizeof(double));
+  s->mac1 = (double*)calloc((size_t)4 * N, sizeof(double));
+  s->Uc = (int*)calloc((size_t)2 * N, sizeof(int));
+  s->Un = (int*)calloc((size_t)2 * N, sizeof(int));
+  s->Uc1 = (int*)calloc((size_t)2 * N, sizeof(int));
+  s->Un1 = (int*)calloc((size_t)2 * N, sizeof(int));
+  s->Us = (int*)calloc((size_t)2 * N, sizeof(int));
+  if (!s->f || !s->g || !s->fp || !s->gp || !s->mac || !s->mac1 || !s->Uc || !s->Un ||
+      !s->Uc1 || !s->Un1 || !s->Us) {
+    orc_destroy(s);
+    return NULL;
+  }
+  s->st.fail_node = -1;
+  return s;
+}
+
+void orc_destroy(orc_sim* s) {
+  if (!s) return;
+  free(s->f); free(s->g); free(s->fp); free(s->gp);
+  free(s->mac); free(s->mac1);
+  free(s->Uc); free(s->Un); free(s->Uc1); free(s->Un1); free(s->Us);
+  free(s);
+}
+
+/* Keeps the lowest failing node index of a pass and its status code. */
+static void record_failure(orc_sim* s, long n, int rc, int* err) {
+#pragma omp critical(orc_fail)
+  {
+    if (*err == 0 || n < s->st.fail_node) {
+      *err = rc;
+      s->st.fail_node = n;
+    }
+  }
+}
+
+/* Kinetic sensor, eq. (DeltaAvg): eps = (1/V) sum_i |f_i - f_i^eq| / f_i^eq,
+ * with tau_f -> tau_f alpha(eps) (Sec. IV.A.2).  The paper gives the
+ * threshold 0.01 above which dissipation is added but not alpha itself.
+ * Reading: alpha is piecewise constant, 1 below 1e-2, then 1.05, 1.35 and
+ * 2 from 1e-1 and 1 upwards. */
+static double sensor_alpha(const double* f, double rho, const double* w) {
+  double eps = 0.0;
+  for (int i = 0; i < ORC_Q; ++i) {
+    double feq = rho * w[i];
+    eps += fabs(f[i] - feq) / feq;
+  }
+  eps /= ORC_Q;
+  if (eps < 1e-2) return 1.0;
+  if (eps < 1e-1) return 1.05;
+  if (eps < 1.0) return 1.35;
+  return 2.0;
+}
+
+/* Moments, lattice selection, equilibrium and collision for every node.
+ * Input: pre-collision populations fp, gp living in lattice Un.
+ * Output: post-collision f, g in lattice Un (now Uc), macros, next lattice. */
+static int collide_all(orc_sim* s) {
+  const orc_params* p = &s->p;
+  const long N = s->N;
+  const double Cv = 1.0 / (p->gamma - 1.0);
+  int err = 0;
+  long calls = 0, iters = 0;
+  long hist[ORC_HIST];
+  memset(hist, 0, sizeof hist);
+#pragma omp parallel for schedule(static) reduction(+ : calls, iters)
+  for (long n = 0; n < N; ++n) {
+    const int Ux = s->Un[2 * n], Uy = s->Un[2 * n + 1];
+    double f[ORC_Q], g[ORC_Q];
+    for (int i = 0; i < ORC_Q; ++i) {
+      f[i] = s->fp[i * N + n];
+      g[i] = s->gp[i * N + n];
+    }
+    /* moments in the frame of the lattice, eq. (polyTemp) */
+    double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+    for (int i = 0; i < ORC_Q; ++i) {
+      rho += f[i];
+      jx += f[i] * XI[i][0];
+      jy += f[i] * XI[i][1];
+      e += (double)(XI[i][0] * XI[i][0] + XI[i][1] * XI[i][1]) * f[i] + g[i];
+    }
+    double upx = jx / rho, upy = jy / rho;
+    double T = (e - rho * (upx * upx + upy * upy)) / (2.0 * rho * Cv);
+    if (!(rho > 0.0) || !(T > 0.0) || !isfinite(rho) || !isfinite(T) ||
+        !isfinite(upx) || !isfinite(upy)) {
+      record_failure(s, n, ORC_ERR_NONPHYSICAL, &err);
+      continue;
+    }
+    double ux = upx + Ux, uy = upy + Uy;
+    /* decomposition for the next streaming, eq. (criterion) */
+    int nUx, nUy;
+    if (p->shift_mode == 1) {
+      nUx = p->fixed_ux;
+      nUy = p->fixed_uy;
+    } else if (p->shift_mode == 2) {
+      nUx = s->Us[2 * n];
+      nUy = s->Us[2 * n + 1];
+    } else {
+      nUx = select_axis(ux, Ux, p->halfwidth);
+      nUy = select_axis(uy, Uy, p->halfwidth);
+    }
+    if (abs(nUx) > p->max_abs_shift || abs(nUy) > p->max_abs_shift) {
+      record_failure(s, n, ORC_ERR_NONPHYSICAL, &err);
+      continue;
+    }
+    /* numerical equilibrium in the current lattice, eqs. (feqNum_8Mom), (gEq) */
+    double w[ORC_Q], lam[ORC_M];
+    int it = 0;
+    int rc = orc_equilibrium(upx, upy, T, NULL, p->newton_tol, p->newton_max_iter, w,
+                             lam, &it);
+    calls += 1;
+    iters += it;
+    if (rc) {
+      record_failure(s, n, rc, &err);
+      continue;
+    }
+#pragma omp atomic
+    hist[it < ORC_HIST ? it : ORC_HIST - 1] += 1;
+    /* BGK collision, eq. (coll), tau = 1/2 + nu / T (App. E) */
+    double tau = 0.5 + p->nu / T;
+    if (p->sensor) tau *= sensor_alpha(f, rho, w);
+    for (int i = 0; i < ORC_Q; ++i) {
+      double feq = rho * w[i];
+      double geq = (2.0 * Cv - ORC_D) * T * feq;
+      s->f[i * N + n] = f[i] - (f[i] - feq) / tau;
+      s->g[i * N + n] = g[i] - (g[i] - geq) / tau;
+    }
+    s->mac1[4 * n + 0] = rho;
+    s->mac1[4 * n + 1] = ux;
+    s->mac1[4 * n + 2] = uy;
+    s->mac1[4 * n + 3] = T;
+    s->Uc1[2 * n] = Ux;
+    s->Uc1[2 * n + 1] = Uy;
+    s->Un1[2 * n] = nUx;
+    s->Un1[2 * n + 1] = nUy;
+  }
+  s->st.newton_calls += calls;
+  s->st.newton_iters += iters;
+  for (int k = 0; k < ORC_HIST; ++k) s->st.hist[k] += hist[k];
+  if (err) return err;
+  double* t = s->mac; s->mac = s->mac1; s->mac1 = t;
+  int* u = s->Uc; s->Uc = s->Uc1; s->Uc1 = u;
+  u = s->Un; s->Un = s->Un1; s->Un1 = u;
+  return ORC_OK;
+}
+
+/* Central differences (Reading: second-order FD of Sec. IV.A.1 are centred,
+ * periodic) of absolute velocity and temperature around node n, taken from
+ * per-node values v[4 * m + k] with k = 1, 2 (u) and 3 (T). */
+static void gradients(const orc_sim* s, const double* v, long n, double du[4],
+                      double dT[2]) {
+  long nx = s->p.nx, ny = s->p.ny;
+  long x = n % nx, y = n / nx;
+  long xp = y * nx + wrap(x + 1, nx), xm = y * nx + wrap(x - 1, nx);
+  long yp = wrap(y + 1, ny) * nx + x, ym = wrap(y - 1, ny) * nx + x;
+  du[0] = 0.5 * (v[4 * xp + 1] - v[4 * xm + 1]);
+  du[1] = 0.5 * (v[4 * yp + 1] - v[4 * ym + 1]);
+  du[2] = 0.5 * (v[4 * xp + 2] - v[4 * xm + 2]);
+  du[3] = 0.5 * (v[4 * yp + 2] - v[4 * ym + 2]);
+  dT[0] = 0.5 * (v[4 * xp + 3] - v[4 * xm + 3]);
+  dT[1] = 0.5 * (v[4 * yp + 3] - v[4 * ym + 3]);
+}
+
+/* Eq. (GradGeneral) applied to a missing post-collision population
+ * (Sec. IV.A.4): macros and gradients at the source x - c_i, equilibrium in
+ * the lattice of the receiving node. */
+static int reconstruct(const orc_sim* s, long src, int Lx, int Ly, int i, double* fi,
+                       double* gi) {
+  double du[4], dT[2], f[ORC_Q], g[ORC_Q];
+  const double* m = s->mac + 4 * src;
+  gradients(s, s->mac, src, du, dT);
+  int rc = orc_grad_populations(&s->p, m[0], m[1], m[2], m[3], du, dT, Lx, Ly, 1, f, g);
+  *fi = f[i];
+  *gi = g[i];
+  return rc;
+}
+
+int orc_init(orc_sim* s, const double* rho, const double* ux, const double* uy,
+             const double* T) {
+  const orc_params* p = &s->p;
+  const long N = s->N;
+  int err = 0;
+  /* Grad initial condition (Sec. IV.A.1): h(0) = h_eq (1 + phi_h) in the
+   * lattice each node selects, gradients of the input fields by central
+   * differences.  Reading: these are pre-collision populations, followed by
+   * a collision, so the stored state is h*(0). */
+  double* v = (double*)malloc(sizeof(double) * 4 * N);
+  if (!v) return ORC_ERR_ARG;
+  for (long n = 0; n < N; ++n) {
+    v[4 * n] = rho[n];
+    v[4 * n + 1] = ux[n];
+    v[4 * n + 2] = uy[n];
+    v[4 * n + 3] = T[n];
+  }
+  memset(&s->st, 0, sizeof s->st);
+  s->st.fail_node = -1;
+#pragma omp parallel for schedule(static)
+  for (long n = 0; n < N; ++n) {
+    int Ux, Uy;
+    if (p->shift_mode == 1) {
+      Ux = p->fixed_ux;
+      Uy = p->fixed_uy;
+    } else if (p->shift_mode == 2) {
+      Ux = s->Us[2 * n];
+      Uy = s->Us[2 * n + 1];
+    } else {
+      Ux = (int)ceil(ux[n] - 0.5);
+      Uy = (int)ceil(uy[n] - 0.5);
+    }
+    if (!isfinite(ux[n]) || !isfinite(uy[n]) || abs(Ux) > p->max_abs_shift ||
+        abs(Uy) > p->max_abs_shift) {
+      record_failure(s, n, ORC_ERR_NONPHYSICAL, &err);
+      continue;
+    }
+    double du[4], dT[2], f[ORC_Q], g[ORC_Q];
+    gradients(s, v, n, du, dT);
+    int rc = orc_grad_populations(p, rho[n], ux[n], uy[n], T[n], du, dT, Ux, Uy, 0, f, g);
+    if (rc) {
+      record_failure(s, n, rc, &err);
+      continue;
+    }
+    for (int i = 0; i < ORC_Q; ++i) {
+      s->fp[i * N + n] = f[i];
+      s->gp[i * N + n] = g[i];
+    }
+    s->Un[2 * n] = Ux;
+    s->Un[2 * n + 1] = Uy;
+  }
+  free(v);
+  if (err) return err;
+  return collide_all(s);
+}
+
+int orc_set_static_shift(orc_sim* s, const int* Ux, const int* Uy) {
+  for (long n = 0; n < s->N; ++n) {
+    s->Us[2 * n] = Ux[n];
+    s->Us[2 * n + 1] = Uy[n];
+  }
+  return ORC_OK;
+}
+
+int orc_step(orc_sim* s, int nsteps) {
+  const long N = s->N;
+  const long nx = s->p.nx, ny = s->p.ny;
+  for (int k = 0; k < nsteps; ++k) {
+    int err = 0;
+    long mism = 0;
+    /* streaming, eq. (stream), pull form: h_i(x, t+1) = h*_i(x - c_i, t) when
+     * x and x - c_i use the same lattice, otherwise eq. (GradGeneral) with
+     * macros and gradients at x - c_i (Sec. IV.A.4). */
+#pragma omp parallel for schedule(static) reduction(+ : mism)
+    for (long n = 0; n < N; ++n) {
+      const long x = n % nx, y = n / nx;
+      const int Ux = s->Un[2 * n], Uy = s->Un[2 * n + 1];
+      for (int i = 0; i < ORC_Q; ++i) {
+        long sx = wrap(x - (XI[i][0] + Ux), nx);
+        long sy = wrap(y - (XI[i][1] + Uy), ny);
+        long src = sy * nx + sx;
+        if (s->Uc[2 * src] == Ux && s->Uc[2 * src + 1] == Uy) {
+          s->fp[i * N + n] = s->f[i * N + src];
+          s->gp[i * N + n] = s->g[i * N + src];
+        } else {
+          mism += 1;
+          int rc = reconstruct(s, src, Ux, Uy, i, &s->fp[i * N + n], &s->gp[i * N + n]);
+          if (rc) record_failure(s, n, rc, &err);
+        }
+      }
+    }
+    s->st.mismatched_links += mism;
+    if (err) return err;
+    int rc = collide_all(s);
+    if (rc) return rc;
+    s->st.steps += 1;
+  }
+  return ORC_OK;
+}
+
+void orc_macros(const orc_sim* s, double* rho, double* ux, double* uy, double* T,
+                int* Ucx, int* Ucy, int* Unx, int* Uny) {
+  for (long n = 0; n < s->N; ++n) {
+    if (rho) rho[n] = s->mac[4 * n];
+    if (ux) ux[n] = s->mac[4 * n + 1];
+    if (uy) uy[n] = s->mac[4 * n + 2];
+    if (T) T[n] = s->mac[4 * n + 3];
+    if (Ucx) Ucx[n] = s->Uc[2 * n];
+    if (Ucy) Ucy[n] = s->Uc[2 * n + 1];
+    if (Unx) Unx[n] = s->Un[2 * n];
+    if (Uny) Uny[n] = s->Un[2 * n + 1];
+  }
+}
+
+void orc_populations(const orc_sim* s, double* f, double* g) {
+  size_t bytes = sizeof(double) * ORC_Q * (size_t)s->N;
+  if (f) memcpy(f, s->f, bytes);
+  if (g) memcpy(g, s->g, bytes);
+}
+
+void orc_conserved(const orc_sim* s, double* out4) {
+  long double m = 0, px = 0, py = 0, en = 0;
+  const long N = s->N;
+  for (long n = 0; n < N; ++n) {
+    for (int i = 0; i < ORC_Q; ++i) {
+      long double f = s->f[i * N + n], g = s->g[i * N + n];
+      long double cx = XI[i][0] + s->Uc[2 * n], cy = XI[i][1] + s->Uc[2 * n + 1];
+      m += f;
+      px += f * cx;
+      py += f * cy;
+      en += 0.5L * ((cx * cx + cy * cy) * f + g);
+    }
+  }
+  out4[0] = (double)m;
+  out4[1] = (double)px;
+  out4[2] = (double)py;
+  out4[3] = (double)en;
+}
+
+void orc_get_stats(const orc_sim* s, orc_stats* out) { *out = s->st; }

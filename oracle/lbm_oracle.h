@@ -1,0 +1,111 @@
+/*
+ * Plain FP64 CPU oracle for the interpolation-free, state-adaptive
+ * compressible lattice Boltzmann method of Coreixas & Latt (arXiv 2009.13426):
+ * D2Q21 lattice, 8-constraint numerical (maximum-entropy) equilibrium,
+ * double-distribution BGK collision, on-grid pull streaming with Grad
+ * reconstruction where neighbouring lattice shifts differ.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
+ * reference the GPU implementation is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code with the GPU path and must never be used as a fallback for it.
+ *
+ * Conventions
+ *  - Grid nx * ny, periodic in x and y; node n = y * nx + x.
+ *  - Populations are stored SoA: h[i * N + n], i in [0, 21).
+ *  - Fields passed in or out are float64 arrays of N values, row-major [ny][nx].
+ *  - All arithmetic is IEEE double, built with -ffp-contract=off.
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_Q 21          /* discrete velocities of D2Q21 */
+#define ORC_M 8           /* constraints of the 8-moment equilibrium */
+#define ORC_D 2           /* physical dimensions */
+#define ORC_HIST 128      /* Newton-iteration histogram bins */
+
+enum {
+  ORC_OK = 0,
+  ORC_ERR_ARG = -1,
+  ORC_ERR_NEWTON = -5,       /* the equilibrium solve did not converge */
+  ORC_ERR_NONPHYSICAL = -6   /* rho <= 0, T <= 0, non-finite, or |U| too large */
+};
+
+typedef struct {
+  int nx, ny;
+  double gamma;          /* heat capacity ratio; Cv = 1/(gamma-1), Cp = gamma Cv */
+  double nu;             /* kinematic viscosity; tau = 1/2 + nu / T per node */
+  int shift_mode;        /* 0: adaptive criterion; 1: one fixed lattice (fixed_ux, fixed_uy);
+                            2: static per-node map set by orc_set_static_shift */
+  int fixed_ux, fixed_uy;
+  double halfwidth;      /* 0.5 reproduces the criterion exactly; > 0.5 adds hysteresis */
+  double newton_tol;     /* max |G_a| per unit density; 1e-12 */
+  int newton_max_iter;
+  int max_abs_shift;     /* |U_alpha| above this is reported as non-physical */
+  int sensor;            /* 1: Knudsen sensor scales tau by alpha(eps_Kn) */
+} orc_params;
+
+typedef struct {
+  long newton_calls;
+  long newton_iters;
+  long mismatched_links;
+  long hist[ORC_HIST];
+  long fail_node;        /* first failing node (lowest index), -1 if none */
+  long steps;
+} orc_stats;
+
+typedef struct orc_sim orc_sim;
+
+/* Velocity table: writes 21 integer components each. */
+void orc_velocities(int* cx, int* cy);
+
+/* Numerical equilibrium per unit density in the frame of the lattice:
+ * minimises sum_i w_i ln(w_i) under the 8 moment constraints for peculiar
+ * velocity (ux, uy) and temperature T.  lam0 (nullable) is an initial guess
+ * for the 8 multipliers.  Outputs w[21], lam[8], Newton iterations used.
+ * Returns ORC_OK, ORC_ERR_NEWTON or ORC_ERR_NONPHYSICAL. */
+int orc_equilibrium(double ux, double uy, double T, const double* lam0,
+                    double tol, int max_iter, double* w, double* lam, int* iters);
+
+/* Exact targets m[8] of the 8 constraints per unit density. */
+void orc_targets(double ux, double uy, double T, double* m);
+
+/* Grad populations h = h_eq (1 + phi) for lattice shift (Lx, Ly) at a state
+ * with gradients du = (dux/dx, dux/dy, duy/dx, duy/dy), dT = (dT/dx, dT/dy).
+ * post != 0 returns post-collision h_eq (1 + (1 - 1/tau) phi) instead.
+ * Writes f[21], g[21]. */
+int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
+                         double T, const double* du, const double* dT, int Lx,
+                         int Ly, int post, double* f, double* g);
+
+/* Lattice shift along one axis for velocity u, previous shift Uprev and
+ * selection half-width (0.5 = eq. criterion without history). */
+int orc_select(double u, int Uprev, double halfwidth);
+
+orc_sim* orc_create(const orc_params* p);
+void orc_destroy(orc_sim* s);
+int orc_init(orc_sim* s, const double* rho, const double* ux, const double* uy,
+             const double* T);
+/* Per-node lattice shifts for shift_mode 2 (the paper's 'static' Sod
+ * configuration, Sec. IV.C.1); call before orc_init. */
+int orc_set_static_shift(orc_sim* s, const int* Ux, const int* Uy);
+int orc_step(orc_sim* s, int nsteps);
+/* Macros at the current time: rho, absolute u, T; lattice tags of the stored
+ * populations (Uc) and of the next pull (Un); any pointer may be NULL. */
+void orc_macros(const orc_sim* s, double* rho, double* ux, double* uy, double* T,
+                int* Ucx, int* Ucy, int* Unx, int* Uny);
+/* Post-collision populations, [i * N + n]. */
+void orc_populations(const orc_sim* s, double* f, double* g);
+/* Sums over the grid of mass, x/y momentum and total energy
+ * (1/2) sum_i (|c_i|^2 f_i + g_i) of the stored populations. */
+void orc_conserved(const orc_sim* s, double* out4);
+void orc_get_stats(const orc_sim* s, orc_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,198 @@
+"""Pins of the oracle's lattice and numerical equilibrium to what the paper
+and the mathematics fix (not to the oracle's own code).
+
+The basis and constraint targets below are written from the paper's
+eqs. (8moments), (G0_8mom)-(G3yaa_8mom) and (feqNum_8Mom) independently of
+oracle/lbm_oracle.c.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+
+def paper_basis(c):
+    """phi(xi) of eq. (feqNum_8Mom) for an (n, 2) array of velocities."""
+    x, y = c[:, 0].astype(float), c[:, 1].astype(float)
+    a2 = x * x + y * y
+    return np.stack([np.ones_like(x), x, y, x * x, x * y, y * y, x * a2, y * a2], 1)
+
+
+def paper_targets(ux, uy, T, D=2):
+    """Right-hand sides of eqs. (G0_8mom)-(G3yaa_8mom) per unit density,
+    with 2E = u_x^2 + u_y^2 + D T (App. C)."""
+    E = 0.5 * (ux * ux + uy * uy + D * T)
+    return np.array([1.0, ux, uy, ux * ux + T, ux * uy, uy * uy + T,
+                     2 * ux * (E + T), 2 * uy * (E + T)])
+
+
+STATES = [(0.0, 0.0, 0.7), (0.3, -0.2, 0.7), (0.5, 0.5, 0.5), (-0.45, 0.1, 1.4),
+          (1.2, 0.0, 0.7), (0.9, -0.8, 1.0), (1.5, 0.0, 0.5), (0.0, -1.5, 1.4)]
+
+
+def test_lattice_is_d2q21_reading(orc):
+    v = orc.velocities()
+    assert v.shape == (21, 2)
+    assert len({tuple(a) for a in v}) == 21
+    assert np.abs(v).max() == 3
+    for ref in [(0, 0), (-1, 0), (1, 1)]:      # Fig. 1 caption reference populations
+        assert tuple(ref) in {tuple(a) for a in v}
+    S = {tuple(a) for a in v}
+    # closed under the square's symmetry group (rotation by 90 deg, reflection)
+    assert {(-b, a) for a, b in S} == S
+    assert {(a, -b) for a, b in S} == S
+    assert np.linalg.matrix_rank(paper_basis(v)) == 8
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES)
+def test_constraints_reproduced_to_roundoff(orc, ux, uy, T):
+    """Sum_i f_eq phi(xi_i) matches the closed forms of the paper to rounding
+    (App. C: criterion 1e-12 leaves constraint errors near 1e-14)."""
+    w, lam, it, rc = orc.equilibrium(ux, uy, T)
+    assert rc == 0
+    assert np.all(w > 0)
+    G = paper_basis(orc.velocities()).T @ w - paper_targets(ux, uy, T)
+    assert np.max(np.abs(G)) <= 2e-14 * max(1.0, np.max(np.abs(paper_targets(ux, uy, T))))
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES)
+def test_exponential_form(orc, ux, uy, T):
+    """ln(w) + 1 lies in the span of the 8 monomials (eq. exponential), and the
+    returned multipliers reproduce w."""
+    v = orc.velocities()
+    P = paper_basis(v)
+    w, lam, it, rc = orc.equilibrium(ux, uy, T)
+    rhs = -(np.log(w) + 1.0)
+    coef, *_ = np.linalg.lstsq(P, rhs, rcond=None)
+    assert np.max(np.abs(P @ coef - rhs)) < 1e-11
+    assert np.allclose(np.exp(-(1.0 + P @ lam)), w, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES[:5])
+def test_unique_root_from_other_guesses(orc, ux, uy, T):
+    """The dual is strictly convex: other starting points give the same EDF."""
+    w0, lam0, _, rc = orc.equilibrium(ux, uy, T)
+    assert rc == 0
+    rng = np.random.default_rng(7)
+    for k in range(3):
+        start = lam0 + rng.normal(scale=0.05, size=8)
+        w, lam, it, rc = orc.equilibrium(ux, uy, T, lam0=start)
+        assert rc == 0
+        assert np.max(np.abs(w - w0) / w0) < 1e-12
+
+
+@pytest.mark.parametrize("T", [0.5, 0.7, 1.0, 1.4])
+def test_rest_state_reduces_to_scalar_equation(orc, T):
+    """At u = 0 symmetry and uniqueness leave w_i proportional to
+    exp(-beta |xi_i|^2), beta solving sum |xi|^2 e^{-beta|xi|^2} / sum
+    e^{-beta|xi|^2} = 2T; solved here by bisection."""
+    v = orc.velocities().astype(float)
+    a2 = (v ** 2).sum(1)
+
+    def mean_a2(beta):
+        e = np.exp(-beta * a2)
+        return (a2 * e).sum() / e.sum()
+
+    lo, hi = 0.0, 50.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mean_a2(mid) > 2 * T:
+            lo = mid
+        else:
+            hi = mid
+    beta = 0.5 * (lo + hi)
+    e = np.exp(-beta * a2)
+    w_ref = e / e.sum()
+    w, lam, it, rc = orc.equilibrium(0.0, 0.0, T)
+    assert rc == 0
+    assert np.max(np.abs(w - w_ref) / w_ref) < 1e-12
+    assert abs(lam[3] - beta) < 1e-10 and abs(lam[5] - beta) < 1e-10
+    assert np.all(np.abs(lam[[1, 2, 4, 6, 7]]) < 1e-12)
+
+
+@pytest.mark.parametrize("U", [(1, 0), (2, -1), (-3, 2)])
+def test_frame_invariance_against_powell_hybrid(orc, U):
+    """The constrained problem written with the shifted velocities
+    c_i = xi_i + U and the absolute velocity u (as eqs. G0..G3 are printed)
+    has the same solution as the oracle's lattice-frame solve at u - U.
+    The absolute-frame problem is solved here by MINPACK's hybrid Powell
+    method (the algorithm family the paper uses, Sec. II.C.2)."""
+    ux, uy, T = U[0] + 0.31, U[1] - 0.27, 0.8
+    c = orc.velocities() + np.array(U)
+    P = paper_basis(c)
+    m = paper_targets(ux, uy, T)
+
+    def G(lam):
+        return P.T @ np.exp(-(1 + P @ lam)) - m
+
+    def J(lam):
+        w = np.exp(-(1 + P @ lam))
+        return -(P * w[:, None]).T @ P
+
+    # start from a Maxwellian-like point written in the absolute frame
+    lam0 = np.zeros(8)
+    lam0[1], lam0[2] = -ux / T, -uy / T
+    lam0[3] = lam0[5] = 0.5 / T
+    lam0[0] = math.log(np.exp(-(P[:, 1:] @ lam0[1:])).sum()) - 1
+    sol = scipy.optimize.root(G, lam0, jac=J, method="hybr", options=dict(xtol=1e-15))
+    assert np.max(np.abs(G(sol.x))) < 1e-12
+    w_abs = np.exp(-(1 + P @ sol.x))
+    w, lam, it, rc = orc.equilibrium(ux - U[0], uy - U[1], T)
+    assert rc == 0
+    assert np.max(np.abs(w - w_abs) / w_abs) < 1e-10
+
+
+def test_solver_envelope_matches_paper_limit(orc):
+    """Sec. III.A.2: with T = 0.7 on the unshifted D2Q21 lattice the root
+    finder fails for u_x >= 2.  The oracle converges below and fails at it."""
+    lim = GOLD["solver_limit_ux"]
+    T = lim["T"]
+    for u in [0.0, 0.5, 1.0, 1.5, 1.8]:
+        assert orc.equilibrium(u, 0.0, T)[3] == 0, u
+    assert orc.equilibrium(lim["value"], 0.0, T)[3] == orc.ERR_NEWTON
+    assert orc.equilibrium(2.5, 0.0, T)[3] == orc.ERR_NEWTON
+
+
+def test_envelope_covers_one_lattice_step(orc):
+    """Every reconstruction across a unit shift needs |u - U| up to 1.5; the
+    solver must converge there over the temperatures the tests use."""
+    for T in [0.5, 0.7, 1.0, 1.4]:
+        for ang in np.linspace(0, 2 * np.pi, 9)[:-1]:
+            for r in [0.5, 1.0, 1.5]:
+                rc = orc.equilibrium(r * math.cos(ang), r * math.sin(ang), T)[3]
+                assert rc == 0, (T, ang, r)
+
+
+def test_unenforced_moment_deviation_is_shift_symmetric(orc):
+    """Sec. III.A.2: near u_x = 0.5 the lattices U_x = 0 and 1 give (here:
+    exactly, by the lattice's reflection symmetry) the same deviation of the
+    non-enforced third-order moment M_xxx = rho u (u^2 + 3T), and it is
+    below the 10 % acceptance threshold at T = T0."""
+    T = GOLD["reference_temperature_D2Q21"]["value"]
+    u = 0.5
+    v = orc.velocities().astype(float)
+    mb = u * (u * u + 3 * T)
+    eps = []
+    for U in (0, 1):
+        w, _, _, rc = orc.equilibrium(u - U, 0.0, T)
+        assert rc == 0
+        cx = v[:, 0] + U
+        eps.append(abs(mb - (w * cx ** 3).sum()) / mb)
+    assert abs(eps[0] - eps[1]) < 1e-13
+    assert eps[0] < GOLD["macro_error_threshold"]["value"]
+
+
+def test_nonphysical_inputs_are_rejected(orc):
+    assert orc.equilibrium(0.1, 0.0, 0.0)[3] == orc.ERR_NONPHYSICAL
+    assert orc.equilibrium(0.1, 0.0, -1.0)[3] == orc.ERR_NONPHYSICAL
+    assert orc.equilibrium(float("nan"), 0.0, 0.7)[3] == orc.ERR_NONPHYSICAL
+
+
+def test_targets_match_paper(orc):
+    for s in STATES:
+        assert np.allclose(orc.targets(*s), paper_targets(*s), rtol=0, atol=1e-15)
