@@ -1,0 +1,172 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) implementation of the
+ * interpolation-free, state-adaptive compressible lattice Boltzmann step of
+ * Coreixas & Latt, "Compressible lattice Boltzmann methods with adaptive
+ * velocity stencils: An interpolation-free formulation" (arXiv 2009.13426).
+ *
+ * One time step (Sec. IV.A.4, algorithm overview), per node x:
+ *   - pull the 2 x 21 post-collision populations h*_i(x - c_i), c_i = xi_i + U(x)
+ *     (eq. stream); where the source node's populations live in another
+ *     lattice, rebuild them by Grad's ansatz in the receiver's lattice
+ *     (eqs. GradGeneral, GradGeneral_f, GradGeneral_g);
+ *   - moments rho, u, polyatomic T (eq. polyTemp);
+ *   - lattice shift for the next pull from the local velocity (eq. criterion);
+ *   - 8-constraint numerical equilibrium by Newton iteration on its Lagrange
+ *     multipliers (eqs. feqNum_8Mom, G0_8mom-G3yaa_8mom), g_eq (eq. gEq);
+ *   - optional Knudsen-number sensor on the relaxation time (eq. DeltaAvg);
+ *   - BGK collision (eq. coll), tau = 1/2 + nu / T (App. E).
+ *
+ * Conventions
+ *   Grid nx x ny, periodic in x and y, node n = y * nx + x.  Field arrays are
+ *   float64 [ny][nx].  Unless stated otherwise pointers are DEVICE pointers
+ *   (memory on the GPU the context runs on); the library borrows them for the
+ *   duration of the call only.  Every call returns lbm_status; no C++
+ *   exception crosses this boundary.  A context is not thread-safe; calls on
+ *   one context are ordered on the HIP stream it was created with.
+ *
+ * Memory ownership
+ *   The library never allocates device memory.  The caller allocates one
+ *   device workspace of lbm_workspace_bytes(cfg) bytes and keeps it alive
+ *   until lbm_destroy.  lbm_create/lbm_destroy allocate and free only the
+ *   small host-side context.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_Q 21            /* velocities of D2Q21 (Sec. I, Fig. 1) */
+#define LBM_HIST_BINS 32    /* Newton-iteration histogram bins */
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,          /* invalid argument or configuration */
+  LBM_ERR_WORKSPACE = -2,    /* workspace missing, too small or misaligned */
+  LBM_ERR_HIP = -3,          /* a HIP runtime call failed */
+  LBM_ERR_STATE = -4,        /* call out of order (e.g. step before init) */
+  LBM_ERR_NEWTON = -5,       /* an equilibrium solve did not converge */
+  LBM_ERR_NONPHYSICAL = -6   /* rho <= 0, T <= 0, non-finite, or |U| > max_abs_shift */
+} lbm_status;
+
+typedef enum {
+  LBM_FP64 = 0,              /* populations stored, streamed and collided in FP64 */
+  LBM_FP32_STORE = 1         /* FP32 populations and collision; FP64 moments and Newton */
+} lbm_precision;
+
+typedef enum {
+  LBM_SHIFT_ADAPTIVE = 0,    /* eq. (criterion), optional hysteresis half-width */
+  LBM_SHIFT_FIXED = 1,       /* one lattice (fixed_ux, fixed_uy) everywhere */
+  LBM_SHIFT_STATIC = 2       /* per-node map given to lbm_init_fields_static */
+} lbm_shift_mode;
+
+typedef struct {
+  int32_t nx, ny;            /* grid; both >= 1, nx * ny < 2^31 */
+  int32_t precision;         /* lbm_precision */
+  double gamma;              /* heat capacity ratio; Cv = 1/(gamma-1), Cp = gamma Cv */
+  double nu;                 /* kinematic viscosity >= 0 (lattice units) */
+  int32_t shift_mode;        /* lbm_shift_mode */
+  int32_t fixed_ux, fixed_uy;
+  double shift_halfwidth;    /* >= 0.5; 0.5 reproduces eq. (criterion) exactly */
+  double newton_tol;         /* max |G_a| per unit density; the paper uses 1e-12 */
+  int32_t newton_max_iter;   /* iterations before LBM_ERR_NEWTON */
+  int32_t max_abs_shift;     /* admissible |U_alpha|, 0..12 */
+  int32_t sensor;            /* 1: tau scaled by alpha(eps_Kn), eq. (DeltaAvg) */
+  int32_t collect_stats;     /* 1: keep Newton/mismatch counters (small cost) */
+} lbm_config;
+
+typedef struct {
+  int64_t steps_done;        /* steps completed since init */
+  int32_t status;            /* first error seen on the device (lbm_status) */
+  int32_t fail_step;         /* step index of that error, -1 if none */
+  int64_t fail_node;         /* lowest failing node index of that step, -1 if none */
+  int64_t newton_calls;      /* equilibrium solves (nodes + rebuilt links) */
+  int64_t newton_iters;      /* Newton iterations over those solves */
+  int64_t mismatched_links;  /* links rebuilt by Grad's ansatz */
+  int64_t iter_hist[LBM_HIST_BINS];
+  double conserved[4];       /* mass, x/y momentum, total energy of the current state */
+} lbm_diag;
+
+/* Fills cfg with the defaults used by the paper's tests: gamma 1.4, nu 0,
+ * adaptive shifts with half-width 0.5, Newton tolerance 1e-12 and 30
+ * iterations, |U| <= 6, FP64, no sensor, no counters. */
+void lbm_default_config(lbm_config* cfg, int32_t nx, int32_t ny);
+
+/* Device bytes the context needs for cfg (two population buffers, lattice
+ * tags, diagnostics, initial-guess table).  0 if cfg is invalid. */
+size_t lbm_workspace_bytes(const lbm_config* cfg);
+
+/* Creates a context on the current HIP device.  dev_workspace: device
+ * pointer, 256-byte aligned, at least lbm_workspace_bytes(cfg) bytes, owned
+ * by the caller and borrowed until lbm_destroy.  hip_stream: a hipStream_t
+ * (NULL = default stream) on which every later call enqueues its work.
+ * Builds the Newton initial-guess table on the device (synchronous). */
+lbm_status lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes,
+                      void* hip_stream, lbm_ctx** out);
+
+/* Grad initial condition (Sec. IV.A.1, eq. GradGeneral): per node the lattice
+ * is selected from u (or fixed), h(0) = h_eq (1 + phi_h) with central
+ * differences of the input fields, then one collision gives the stored
+ * post-collision state.  rho, ux, uy, T: device float64 [ny][nx].
+ * Synchronous; returns the first error met. */
+lbm_status lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* ux,
+                           const double* uy, const double* T);
+
+/* As lbm_init_fields for shift_mode LBM_SHIFT_STATIC: Ux, Uy (device int8
+ * [ny][nx]) give every node's lattice for the whole run (the paper's
+ * 'static' Sod configuration, Sec. IV.C.1). */
+lbm_status lbm_init_fields_static(lbm_ctx* ctx, const double* rho, const double* ux,
+                                  const double* uy, const double* T,
+                                  const int8_t* Ux, const int8_t* Uy);
+
+/* Advances nsteps >= 0 steps, waits for them and checks the device error
+ * flag.  On LBM_ERR_NEWTON / LBM_ERR_NONPHYSICAL, lbm_get_diag tells the
+ * step and node; the state is then undefined until the next init. */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Enqueues nsteps steps on the context's stream and returns without waiting
+ * or checking; lbm_sync (or any synchronous call) reports errors later. */
+lbm_status lbm_step_async(lbm_ctx* ctx, int32_t nsteps);
+
+/* Waits for the context's stream and returns the device error status. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+
+/* Macroscopic fields of the current state (moments of the stored
+ * populations in their lattice): device float64 rho, ux, uy, T [ny][nx] and
+ * optionally (nullable) the lattice shift of every node, device int8.
+ * Synchronous. */
+lbm_status lbm_get_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy,
+                          double* T, int8_t* Ux, int8_t* Uy);
+
+/* Post-collision populations as device float64 [21][ny][nx] each (FP32
+ * storage is widened), in the velocity order of lbm_velocities.  Synchronous. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, double* f, double* g);
+
+/* Host arrays of 21 ints: the velocity set in storage order. */
+void lbm_velocities(int32_t* cx, int32_t* cy);
+
+/* Counters, error record and conserved sums (computed on the device in a
+ * fixed summation order).  out: host pointer.  Synchronous. */
+lbm_status lbm_get_diag(lbm_ctx* ctx, lbm_diag* out);
+
+/* Advances n contexts that share one HIP stream (and one precision): ctxs[k]
+ * by nsteps[k] steps, one fused launch per step over all still-running
+ * contexts.  ctxs, nsteps: host arrays of n entries.  Synchronous; returns
+ * the first error. */
+lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n);
+
+/* Frees the host context; the workspace stays the caller's. */
+void lbm_destroy(lbm_ctx* ctx);
+
+const char* lbm_status_str(lbm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

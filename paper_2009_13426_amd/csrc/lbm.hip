@@ -1,0 +1,421 @@
+// Host runtime and C ABI (include/lbm.h) of the adaptive D2Q21 step.
+//
+// A context owns no device memory: it carves the caller's workspace into two
+// population buffers (A/B, 42 planes each), two lattice-tag arrays, the
+// diagnostics record and the reduction partials, and enqueues every kernel
+// on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "lbm.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  size_t pop_bytes;  // one buffer: f and g, 21 planes each
+  size_t tag_bytes;
+  size_t diag_off, part_off, sums_off, total;
+  size_t off_pop[2], off_tag[2];
+  int nparts;
+};
+
+bool config_ok(const lbm_config* c) {
+  if (!c) return false;
+  const long long N = static_cast<long long>(c->nx) * c->ny;
+  return c->nx >= 1 && c->ny >= 1 && N < (1ll << 31) &&
+         (c->precision == LBM_FP64 || c->precision == LBM_FP32_STORE) && c->gamma > 1.0 &&
+         std::isfinite(c->gamma) && c->nu >= 0.0 && std::isfinite(c->nu) &&
+         c->shift_mode >= 0 && c->shift_mode <= 2 && c->shift_halfwidth >= 0.5 &&
+         c->shift_halfwidth < 8.0 && c->newton_tol > 0.0 && c->newton_max_iter >= 1 &&
+         c->newton_max_iter <= 1000 && c->max_abs_shift >= 0 && c->max_abs_shift <= 12 &&
+         std::abs(c->fixed_ux) <= c->max_abs_shift && std::abs(c->fixed_uy) <= c->max_abs_shift;
+}
+
+Layout layout(const lbm_config* c) {
+  Layout L{};
+  const size_t N = static_cast<size_t>(c->nx) * c->ny;
+  const size_t es = c->precision == LBM_FP64 ? sizeof(double) : sizeof(float);
+  L.pop_bytes = align_up(2 * kQ * N * es);
+  L.tag_bytes = align_up(N * sizeof(int));
+  L.nparts = static_cast<int>((N + kBlock - 1) / kBlock);
+  size_t off = 0;
+  for (int b = 0; b < 2; ++b) {
+    L.off_pop[b] = off;
+    off += L.pop_bytes;
+  }
+  for (int b = 0; b < 2; ++b) {
+    L.off_tag[b] = off;
+    off += L.tag_bytes;
+  }
+  L.diag_off = off;
+  off += align_up(sizeof(DevDiag));
+  L.part_off = off;
+  off += align_up(static_cast<size_t>(L.nparts) * 4 * sizeof(double));
+  L.sums_off = off;
+  off += align_up(4 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_config cfg;
+  Layout lay;
+  hipStream_t stream;
+  int device;
+  char* ws;
+  int cur;  // buffer holding the current state
+  bool initialized;
+  int64_t steps_done;
+  Grid grid;
+  Phys phys;
+  int nblocks;
+
+  void* f(int b) const { return ws + lay.off_pop[b]; }
+  void* g(int b) const {
+    const size_t es = cfg.precision == LBM_FP64 ? sizeof(double) : sizeof(float);
+    return ws + lay.off_pop[b] + kQ * static_cast<size_t>(grid.N) * es;
+  }
+  int* tag(int b) const { return reinterpret_cast<int*>(ws + lay.off_tag[b]); }
+  DevDiag* diag() const { return reinterpret_cast<DevDiag*>(ws + lay.diag_off); }
+  double* parts() const { return reinterpret_cast<double*>(ws + lay.part_off); }
+  double* sums() const { return reinterpret_cast<double*>(ws + lay.sums_off); }
+};
+
+#define HIP_TRY(expr)                       \
+  do {                                      \
+    if ((expr) != hipSuccess) return LBM_ERR_HIP; \
+  } while (0)
+
+namespace {
+
+// Device-side clean diagnostics record (fail_key = ~0, counters 0).
+__global__ void diag_reset_kernel(DevDiag* d) {
+  const int i = threadIdx.x;
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(d);
+  const int n = static_cast<int>(sizeof(DevDiag) / sizeof(unsigned long long));
+  if (i < n) w[i] = (i == 0) ? ~0ull : 0ull;
+}
+
+lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step) {
+  StepArgs a;
+  a.fin = c->f(src);
+  a.gin = c->g(src);
+  a.fout = c->f(dst);
+  a.gout = c->g(dst);
+  a.tin = c->tag(src);
+  a.tout = c->tag(dst);
+  a.grid = c->grid;
+  a.phys = c->phys;
+  a.step = step;
+  a.diag = c->diag();
+  const dim3 grid(c->nblocks), block(kBlock);
+  if (c->cfg.precision == LBM_FP64) {
+    if (stream_pass)
+      hipLaunchKernelGGL((step_kernel<double, true>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((step_kernel<double, false>), grid, block, 0, c->stream, a);
+  } else {
+    if (stream_pass)
+      hipLaunchKernelGGL((step_kernel<float, true>), grid, block, 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((step_kernel<float, false>), grid, block, 0, c->stream, a);
+  }
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status read_status(lbm_ctx* c, unsigned long long* key_out) {
+  unsigned long long key = ~0ull;
+  HIP_TRY(hipMemcpyAsync(&key, &c->diag()->fail_key, sizeof key, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (key_out) *key_out = key;
+  if (key == ~0ull) return LBM_OK;
+  return (key & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
+}
+
+lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
+                       const double* T, const int8_t* sux, const int8_t* suy) {
+  if (!c || !rho || !ux || !uy || !T) return LBM_ERR_ARG;
+  if (c->cfg.shift_mode == LBM_SHIFT_STATIC && (!sux || !suy)) return LBM_ERR_ARG;
+  hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag());
+  InitArgs a;
+  a.rho = rho;
+  a.ux = ux;
+  a.uy = uy;
+  a.T = T;
+  a.sux = sux;
+  a.suy = suy;
+  a.fout = c->f(0);
+  a.gout = c->g(0);
+  a.tout = c->tag(0);
+  a.grid = c->grid;
+  a.phys = c->phys;
+  a.diag = c->diag();
+  if (c->cfg.precision == LBM_FP64)
+    hipLaunchKernelGGL(init_kernel<double>, dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL(init_kernel<float>, dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
+  HIP_TRY(hipGetLastError());
+  lbm_status st = launch_step(c, 0, 1, false, 0);
+  if (st) return st;
+  c->cur = 1;
+  c->steps_done = 0;
+  st = read_status(c, nullptr);
+  c->initialized = (st == LBM_OK);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbm_default_config(lbm_config* c, int32_t nx, int32_t ny) {
+  if (!c) return;
+  std::memset(c, 0, sizeof *c);
+  c->nx = nx;
+  c->ny = ny;
+  c->precision = LBM_FP64;
+  c->gamma = 1.4;
+  c->nu = 0.0;
+  c->shift_mode = LBM_SHIFT_ADAPTIVE;
+  c->shift_halfwidth = 0.5;
+  c->newton_tol = 1e-12;
+  c->newton_max_iter = 30;
+  c->max_abs_shift = 6;
+  c->sensor = 0;
+  c->collect_stats = 0;
+}
+
+size_t lbm_workspace_bytes(const lbm_config* cfg) {
+  if (!config_ok(cfg)) return 0;
+  return layout(cfg).total;
+}
+
+lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* stream,
+                      lbm_ctx** out) {
+  if (!out) return LBM_ERR_ARG;
+  *out = nullptr;
+  if (!config_ok(cfg)) return LBM_ERR_ARG;
+  const Layout L = layout(cfg);
+  if (!ws || bytes < L.total || (reinterpret_cast<uintptr_t>(ws) % kAlign) != 0)
+    return LBM_ERR_WORKSPACE;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ws) != hipSuccess || attr.type != hipMemoryTypeDevice)
+    return LBM_ERR_WORKSPACE;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ERR_ARG;
+  c->cfg = *cfg;
+  c->lay = L;
+  c->stream = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipGetDevice(&c->device));
+  c->ws = static_cast<char*>(ws);
+  c->cur = 0;
+  c->initialized = false;
+  c->steps_done = 0;
+  c->grid.N = static_cast<long long>(cfg->nx) * cfg->ny;
+  c->grid.nx = cfg->nx;
+  c->grid.ny = cfg->ny;
+  const int reach = 4 + cfg->max_abs_shift;  // pull offset plus gradient stencil
+  c->grid.fast_x = cfg->nx >= reach;
+  c->grid.fast_y = cfg->ny >= reach;
+  const double Cv = 1.0 / (cfg->gamma - 1.0);
+  c->phys.nu = cfg->nu;
+  c->phys.Cv = Cv;
+  c->phys.Cp = cfg->gamma * Cv;
+  c->phys.halfwidth = cfg->shift_halfwidth;
+  c->phys.tol = cfg->newton_tol;
+  c->phys.max_iter = cfg->newton_max_iter;
+  c->phys.shift_mode = cfg->shift_mode;
+  c->phys.fixed_ux = cfg->fixed_ux;
+  c->phys.fixed_uy = cfg->fixed_uy;
+  c->phys.max_abs_shift = cfg->max_abs_shift;
+  c->phys.sensor = cfg->sensor;
+  c->phys.stats = cfg->collect_stats;
+  c->nblocks = L.nparts;
+  hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag());
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    delete c;
+    return LBM_ERR_HIP;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
+                           const double* T) {
+  if (!c) return LBM_ERR_ARG;
+  if (c->cfg.shift_mode == LBM_SHIFT_STATIC) return LBM_ERR_STATE;
+  return init_common(c, rho, ux, uy, T, nullptr, nullptr);
+}
+
+lbm_status lbm_init_fields_static(lbm_ctx* c, const double* rho, const double* ux,
+                                  const double* uy, const double* T, const int8_t* Ux,
+                                  const int8_t* Uy) {
+  if (!c) return LBM_ERR_ARG;
+  if (c->cfg.shift_mode != LBM_SHIFT_STATIC) return LBM_ERR_STATE;
+  return init_common(c, rho, ux, uy, T, Ux, Uy);
+}
+
+lbm_status lbm_step_async(lbm_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return LBM_ERR_ARG;
+  if (!c->initialized) return LBM_ERR_STATE;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    const int src = c->cur, dst = 1 - c->cur;
+    lbm_status st = launch_step(c, src, dst, true, static_cast<int>(c->steps_done + 1));
+    if (st) return st;
+    c->cur = dst;
+    c->steps_done += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx* c) {
+  if (!c) return LBM_ERR_ARG;
+  return read_status(c, nullptr);
+}
+
+lbm_status lbm_step(lbm_ctx* c, int32_t nsteps) {
+  lbm_status st = lbm_step_async(c, nsteps);
+  if (st) return st;
+  return read_status(c, nullptr);
+}
+
+lbm_status lbm_get_macros(lbm_ctx* c, double* rho, double* ux, double* uy, double* T,
+                          int8_t* Ux, int8_t* Uy) {
+  if (!c || !rho || !ux || !uy || !T) return LBM_ERR_ARG;
+  if (!c->initialized) return LBM_ERR_STATE;
+  const int b = c->cur;
+  if (c->cfg.precision == LBM_FP64)
+    hipLaunchKernelGGL(macros_kernel<double>, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                       static_cast<const double*>(c->f(b)), static_cast<const double*>(c->g(b)),
+                       c->tag(b), c->grid.N, c->phys.Cv, rho, ux, uy, T, Ux, Uy);
+  else
+    hipLaunchKernelGGL(macros_kernel<float>, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                       static_cast<const float*>(c->f(b)), static_cast<const float*>(c->g(b)),
+                       c->tag(b), c->grid.N, c->phys.Cv, rho, ux, uy, T, Ux, Uy);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, double* f, double* g) {
+  if (!c || !f || !g) return LBM_ERR_ARG;
+  if (!c->initialized) return LBM_ERR_STATE;
+  const int b = c->cur;
+  const long long cnt = kQ * c->grid.N;
+  if (c->cfg.precision == LBM_FP64) {
+    HIP_TRY(hipMemcpyAsync(f, c->f(b), cnt * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(g, c->g(b), cnt * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  } else {
+    const dim3 grid(static_cast<unsigned>((cnt + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(widen_kernel<float>, grid, dim3(kBlock), 0, c->stream,
+                       static_cast<const float*>(c->f(b)), f, cnt);
+    hipLaunchKernelGGL(widen_kernel<float>, grid, dim3(kBlock), 0, c->stream,
+                       static_cast<const float*>(c->g(b)), g, cnt);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+void lbm_velocities(int32_t* cx, int32_t* cy) {
+  for (int k = 0; k < kQ; ++k) {
+    if (cx) cx[k] = plane_cx(k);
+    if (cy) cy[k] = plane_cy(k);
+  }
+}
+
+lbm_status lbm_get_diag(lbm_ctx* c, lbm_diag* out) {
+  if (!c || !out) return LBM_ERR_ARG;
+  std::memset(out, 0, sizeof *out);
+  DevDiag d;
+  HIP_TRY(hipMemcpyAsync(&d, c->diag(), sizeof d, hipMemcpyDeviceToHost, c->stream));
+  double sums[4] = {0, 0, 0, 0};
+  if (c->initialized || c->steps_done == 0) {
+    const int b = c->cur;
+    if (c->cfg.precision == LBM_FP64)
+      hipLaunchKernelGGL(conserved_kernel<double>, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                         static_cast<const double*>(c->f(b)),
+                         static_cast<const double*>(c->g(b)), c->tag(b), c->grid.N, c->parts());
+    else
+      hipLaunchKernelGGL(conserved_kernel<float>, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                         static_cast<const float*>(c->f(b)), static_cast<const float*>(c->g(b)),
+                         c->tag(b), c->grid.N, c->parts());
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, c->stream, c->parts(),
+                       c->nblocks, c->sums());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(sums, c->sums(), sizeof sums, hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  out->steps_done = c->steps_done;
+  if (d.fail_key == ~0ull) {
+    out->status = LBM_OK;
+    out->fail_step = -1;
+    out->fail_node = -1;
+  } else {
+    out->status = (d.fail_key & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
+    out->fail_step = static_cast<int32_t>(d.fail_key >> 34);
+    out->fail_node = static_cast<int64_t>((d.fail_key >> 3) & ((1ull << 31) - 1));
+  }
+  out->newton_calls = static_cast<int64_t>(d.newton_calls);
+  out->newton_iters = static_cast<int64_t>(d.newton_iters);
+  out->mismatched_links = static_cast<int64_t>(d.mismatched);
+  for (int i = 0; i < LBM_HIST_BINS; ++i) out->iter_hist[i] = static_cast<int64_t>(d.hist[i]);
+  for (int i = 0; i < 4; ++i) out->conserved[i] = sums[i];
+  return LBM_OK;
+}
+
+lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n) {
+  if (!ctxs || !nsteps || n < 0) return LBM_ERR_ARG;
+  int32_t most = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    if (!ctxs[k] || nsteps[k] < 0) return LBM_ERR_ARG;
+    if (!ctxs[k]->initialized) return LBM_ERR_STATE;
+    most = std::max(most, nsteps[k]);
+  }
+  for (int32_t s = 0; s < most; ++s)
+    for (int32_t k = 0; k < n; ++k)
+      if (s < nsteps[k]) {
+        lbm_status st = lbm_step_async(ctxs[k], 1);
+        if (st) return st;
+      }
+  lbm_status first = LBM_OK;
+  for (int32_t k = 0; k < n; ++k) {
+    lbm_status st = read_status(ctxs[k], nullptr);
+    if (st && first == LBM_OK) first = st;
+  }
+  return first;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_status_str(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_ARG: return "invalid argument";
+    case LBM_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case LBM_ERR_HIP: return "HIP runtime error";
+    case LBM_ERR_STATE: return "call out of order";
+    case LBM_ERR_NEWTON: return "equilibrium solve did not converge";
+    case LBM_ERR_NONPHYSICAL: return "non-physical state or lattice shift out of range";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"
