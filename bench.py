@@ -1,0 +1,158 @@
+"""Throughput of the adaptive D2Q21 step on one MI355X.
+
+Workload: the seeded four-quadrant Riemann problem on a 4096 x 4096 periodic
+grid (densities in [0.5, 1.5], pressures in [0.03, 1.5], common velocity up
+to Mach 3), Knudsen sensor on, nu = 1e-3, adaptive lattice shifts.  A step is
+one pass of the whole hot path over every node (pull, Grad rebuild at shift
+interfaces, moments, shift selection, Newton equilibrium, BGK, store).
+
+The headline value is MLUPS (million lattice-node updates per second) of
+the FP32-storage form (FP32 populations and collision, FP64 moments and
+Newton); the FP64 form is timed the same way and reported beside it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--size L] [--no-cpu]
+
+One JSON line on stdout.  Inputs are resident on the GPU before timing
+starts; the timed region is K steps between two synchronisations, and the
+step kernel's own average duration is measured with HIP events on the stream
+the library launches on.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+Q = 21
+
+
+def bytes_per_node(precision):
+    """Algorithmic HBM bytes per node update of the step kernel: read and
+    write 2 x 21 populations, read and write the node's own lattice tag."""
+    es = 8 if precision == "fp64" else 4
+    return 2 * 2 * Q * es + 2 * 4
+
+
+def time_form(lbm, torch, wl, precision, steps, warmup):
+    sim = lbm.Sim.from_workload(wl, precision=precision)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.step_async(steps)
+    ev1.record(sim.stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = ev0.elapsed_time(ev1) / steps
+    d = sim.diag()
+    nodes = wl.nx * wl.ny
+    out = dict(ms_per_step=wall * 1e3 / steps, kernel_ms=kern_ms,
+               mlups=nodes * steps / wall / 1e6,
+               conserved=d["conserved"], status=d["status"])
+    sim.close()
+    return out
+
+
+def stats_pass(lbm, wl, precision, steps):
+    """Newton iterations and rebuilt links per node over a short window."""
+    sim = lbm.Sim.from_workload(wl, precision=precision, stats=True)
+    sim.step(steps)
+    d = sim.diag()
+    nodes = wl.nx * wl.ny * steps
+    sim.close()
+    return dict(newton_iters_per_solve=d["newton_iters"] / max(d["newton_calls"], 1),
+                solves_per_node=d["newton_calls"] / nodes,
+                rebuilt_links_per_node=d["mismatched_links"] / nodes)
+
+
+def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
+    """The FP64 oracle, as it is, on a bounded sample of the same workload:
+    a 511 x 511 periodic crop around the quadrant corner, stepped until about
+    seconds_target have passed (at most max_steps, which keeps the crop
+    clear of the wave collisions its smaller periodic box would bring)."""
+    import oracle
+    half = 255
+    sample = wl_full.window(wl_full.nx // 2, wl_full.ny // 2, half)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    s = oracle.Sim.from_workload(sample)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds_target and n < max_steps:
+        s.step(2)
+        n += 2
+    dt = time.perf_counter() - t0
+    nodes = sample.nx * sample.ny
+    return dict(value=round(nodes * n / dt / 1e6, 4), unit="MLUPS", cores=threads,
+                kind="oracle",
+                sample=f"{sample.nx}x{sample.ny} periodic crop of the same initial field, "
+                       f"{n} steps, FP64, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--forms", default="fp32,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "slab decomposition is a design, not a build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2009_13426_amd as lbm
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.four_quadrant(args.size, args.warmup + args.steps)
+    res = {}
+    for form in args.forms.split(","):
+        print(f"[bench] timing {form} {args.size}^2, warmup {args.warmup}, steps {args.steps}",
+              file=sys.stderr, flush=True)
+        res[form] = time_form(lbm, torch, wl, form, args.steps, args.warmup)
+        print(f"[bench] {form}: {res[form]['mlups']:.1f} MLUPS, "
+              f"kernel {res[form]['kernel_ms']:.3f} ms/step", file=sys.stderr, flush=True)
+    head = "fp32" if "fp32" in res else next(iter(res))
+    print("[bench] counters pass", file=sys.stderr, flush=True)
+    counters = {f: stats_pass(lbm, wl, f, 5) for f in res}
+
+    nodes = wl.nx * wl.ny
+    ach = bytes_per_node(head) * nodes / (res[head]["kernel_ms"] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl)
+
+    line = dict(
+        metric="MLUPS of D2Q21 adaptive step (FP64 vs FP32-store); p50/p99 job latency",
+        value=round(res[head]["mlups"], 2), unit="MLUPS", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(res[head]["ms_per_step"], 4),
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32-store/f64-newton" if head == "fp32" else "f64", data="synthetic",
+        config=dict(workload=f"four-quadrant Riemann {args.size}x{args.size}, D2Q21 adaptive "
+                             f"shifts, Knudsen sensor, nu={wl.nu:g}, seeded draw",
+                    nodes=nodes, precision=head),
+        roofline=roofline, cpu_baseline=cpu,
+        forms={f: dict(mlups=round(r["mlups"], 2), kernel_ms=round(r["kernel_ms"], 4),
+                       hbm_gbs=round(bytes_per_node(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9, 1),
+                       bytes_per_node=bytes_per_node(f), **counters[f])
+               for f, r in res.items()},
+    )
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,10 +12,21 @@
 // Every entry of G and H is one of the 28 monomial moments
 // M_pq = sum_i w_i x_i^p y_i^q, p + q <= 6; with the +- pairing the even ones
 // come from S_p = w+ + w- and the odd ones from D_p = w+ - w-, and all
-// velocity components are compile-time constants.  H is factored by LDL^T.
-// The loop stops when max_a |G_a| <= tol and then applies the final Newton
-// correction to the weights to first order (w_i *= 1 - delta . phi_i), which
-// leaves the constraints satisfied to rounding.
+// velocity components are compile-time constants.  H is factored in place by
+// LDL^T.  The loop stops when max_a |G_a| <= tol and then applies the final
+// Newton correction to the weights to first order (w_i *= 1 - delta . phi_i),
+// which leaves the constraints satisfied to rounding.
+//
+// Two drivers share these pieces:
+//   solve_robust  lattice-Maxwellian start, weights always recomputed from
+//                 the multipliers with the FP64 exp (table build, init);
+//   solve_fast    start from an interpolated table of lambda - lambda_Maxwell,
+//                 weights carried (not multipliers): later updates
+//                 w *= exp(-delta . phi) by a degree-7 polynomial while
+//                 |delta . phi| < 0.03 (truncation below 1e-17 relative), the
+//                 FP64 exp otherwise; H is accumulated straight from the
+//                 weights, one +- pair at a time.
+// Both stop on the same criterion, so both reach the unique root to rounding.
 #pragma once
 
 #include "lattice.hpp"
@@ -62,6 +73,45 @@ __device__ __forceinline__ void linear_update(const double (&d)[kM], Weights& w)
   }
 }
 
+// exp(-z) for |z| < 0.03 by its Taylor polynomial of degree 7.
+__device__ __forceinline__ double expm_small(double z) {
+  const double t = -z;
+  double p = 1.0 / 5040.0;
+  p = __builtin_fma(p, t, 1.0 / 720.0);
+  p = __builtin_fma(p, t, 1.0 / 120.0);
+  p = __builtin_fma(p, t, 1.0 / 24.0);
+  p = __builtin_fma(p, t, 1.0 / 6.0);
+  p = __builtin_fma(p, t, 0.5);
+  p = __builtin_fma(p, t, 1.0);
+  p = __builtin_fma(p, t, 1.0);
+  return p;
+}
+
+// largest |d . phi_i| over the velocities
+template <int p = 0>
+__device__ __forceinline__ double max_step_exponent(const double (&d)[kM], double acc) {
+  if constexpr (p == kPairs) {
+    return fmax(acc, fabs(d[0]));
+  } else {
+    double e, o;
+    pair_exponent<p>(d, 0.0, e, o);
+    return max_step_exponent<p + 1>(d, fmax(acc, fabs(e) + fabs(o)));
+  }
+}
+
+// w_i *= exp(-d . phi_i) with the small-argument polynomial
+template <int p = 0>
+__device__ __forceinline__ void poly_update(const double (&d)[kM], Weights& w) {
+  if constexpr (p == 0) w.w0 *= expm_small(d[0]);
+  if constexpr (p < kPairs) {
+    double e, o;
+    pair_exponent<p>(d, 0.0, e, o);
+    w.wp[p] *= expm_small(e + o);
+    w.wm[p] *= expm_small(e - o);
+    poly_update<p + 1>(d, w);
+  }
+}
+
 template <int P, int Qy, int p = 0>
 __device__ __forceinline__ double mom_acc(double acc, const double (&S)[kPairs],
                                           const double (&D)[kPairs]) {
@@ -82,22 +132,164 @@ __device__ __forceinline__ double mom(const double (&S)[kPairs], const double (&
   return mom_acc<P, Qy>((P + Qy == 0) ? w0 : 0.0, S, D);
 }
 
+__device__ __forceinline__ void pair_sums(const Weights& w, double (&S)[kPairs],
+                                          double (&D)[kPairs]) {
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    S[p] = w.wp[p] + w.wm[p];
+    D[p] = w.wp[p] - w.wm[p];
+  }
+}
+
+// Moments up to third order and the residual G; returns max |G_a|.
+struct LowMoments {
+  double M00, M10, M01, M20, M11, M02, M30, M21, M12, M03;
+};
+
+__device__ __forceinline__ double residual(const double (&S)[kPairs], const double (&D)[kPairs],
+                                           double w0, const double (&m)[kM], LowMoments& L,
+                                           double (&G)[kM]) {
+  L.M00 = mom<0, 0>(S, D, w0);
+  L.M10 = mom<1, 0>(S, D, w0);
+  L.M01 = mom<0, 1>(S, D, w0);
+  L.M20 = mom<2, 0>(S, D, w0);
+  L.M11 = mom<1, 1>(S, D, w0);
+  L.M02 = mom<0, 2>(S, D, w0);
+  L.M30 = mom<3, 0>(S, D, w0);
+  L.M21 = mom<2, 1>(S, D, w0);
+  L.M12 = mom<1, 2>(S, D, w0);
+  L.M03 = mom<0, 3>(S, D, w0);
+  G[0] = L.M00 - m[0];
+  G[1] = L.M10 - m[1];
+  G[2] = L.M01 - m[2];
+  G[3] = L.M20 - m[3];
+  G[4] = L.M11 - m[4];
+  G[5] = L.M02 - m[5];
+  G[6] = L.M30 + L.M12 - m[6];
+  G[7] = L.M21 + L.M03 - m[7];
+  double r = 0.0;
+#pragma unroll
+  for (int a = 0; a < kM; ++a) r = fmax(r, fabs(G[a]));
+  return r;
+}
+
+// Packed lower triangle of the symmetric 8x8 matrix: (i, j), j <= i.
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+constexpr int kTri = kM * (kM + 1) / 2;
+
+// Hessian in the basis (1, x, y, x2, xy, y2, x|xi|^2, y|xi|^2).
+__device__ __forceinline__ void hessian(const double (&S)[kPairs], const double (&D)[kPairs],
+                                        double w0, const LowMoments& L, double (&A)[kTri]) {
+  const double M40 = mom<4, 0>(S, D, w0), M31 = mom<3, 1>(S, D, w0), M22 = mom<2, 2>(S, D, w0);
+  const double M13 = mom<1, 3>(S, D, w0), M04 = mom<0, 4>(S, D, w0);
+  const double M50 = mom<5, 0>(S, D, w0), M41 = mom<4, 1>(S, D, w0), M32 = mom<3, 2>(S, D, w0);
+  const double M23 = mom<2, 3>(S, D, w0), M14 = mom<1, 4>(S, D, w0), M05 = mom<0, 5>(S, D, w0);
+  const double M60 = mom<6, 0>(S, D, w0), M51 = mom<5, 1>(S, D, w0), M42 = mom<4, 2>(S, D, w0);
+  const double M33 = mom<3, 3>(S, D, w0), M24 = mom<2, 4>(S, D, w0), M15 = mom<1, 5>(S, D, w0);
+  const double M06 = mom<0, 6>(S, D, w0);
+  A[tri(0, 0)] = L.M00;
+  A[tri(1, 0)] = L.M10; A[tri(1, 1)] = L.M20;
+  A[tri(2, 0)] = L.M01; A[tri(2, 1)] = L.M11; A[tri(2, 2)] = L.M02;
+  A[tri(3, 0)] = L.M20; A[tri(3, 1)] = L.M30; A[tri(3, 2)] = L.M21; A[tri(3, 3)] = M40;
+  A[tri(4, 0)] = L.M11; A[tri(4, 1)] = L.M21; A[tri(4, 2)] = L.M12; A[tri(4, 3)] = M31;
+  A[tri(4, 4)] = M22;
+  A[tri(5, 0)] = L.M02; A[tri(5, 1)] = L.M12; A[tri(5, 2)] = L.M03; A[tri(5, 3)] = M22;
+  A[tri(5, 4)] = M13; A[tri(5, 5)] = M04;
+  A[tri(6, 0)] = L.M30 + L.M12; A[tri(6, 1)] = M40 + M22; A[tri(6, 2)] = M31 + M13;
+  A[tri(6, 3)] = M50 + M32; A[tri(6, 4)] = M41 + M23; A[tri(6, 5)] = M32 + M14;
+  A[tri(6, 6)] = M60 + 2.0 * M42 + M24;
+  A[tri(7, 0)] = L.M21 + L.M03; A[tri(7, 1)] = M31 + M13; A[tri(7, 2)] = M22 + M04;
+  A[tri(7, 3)] = M41 + M23; A[tri(7, 4)] = M32 + M14; A[tri(7, 5)] = M23 + M05;
+  A[tri(7, 6)] = M51 + 2.0 * M33 + M15; A[tri(7, 7)] = M42 + 2.0 * M24 + M06;
+}
+
+// 1/x to full double precision: hardware estimate plus two Newton-Raphson steps.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// In-place LDL^T: strict lower part of A becomes L, id holds 1/D.
+__device__ __forceinline__ bool ldl_factor(double (&A)[kTri], double (&id)[kM]) {
+  bool spd = true;
+#pragma unroll
+  for (int j = 0; j < kM; ++j) {
+    double t[kM];
+#pragma unroll
+    for (int k = 0; k < j; ++k) t[k] = A[tri(j, k)] * A[tri(k, k)];  // L_jk d_k
+    double dj = A[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj = __builtin_fma(-A[tri(j, k)], t[k], dj);
+    spd = spd && (dj > 0.0);
+    A[tri(j, j)] = dj;
+    id[j] = rcp64(dj);
+#pragma unroll
+    for (int i = j + 1; i < kM; ++i) {
+      double v = A[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v = __builtin_fma(-A[tri(i, k)], t[k], v);
+      A[tri(i, j)] = v * id[j];
+    }
+  }
+  return spd;
+}
+
+__device__ __forceinline__ void ldl_solve(const double (&A)[kTri], const double (&id)[kM],
+                                          const double (&G)[kM], double (&d)[kM]) {
+#pragma unroll
+  for (int i = 0; i < kM; ++i) {
+    double v = G[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v = __builtin_fma(-A[tri(i, k)], d[k], v);
+    d[i] = v;
+  }
+#pragma unroll
+  for (int i = 0; i < kM; ++i) d[i] *= id[i];
+#pragma unroll
+  for (int i = kM - 1; i >= 0; --i) {
+    double v = d[i];
+#pragma unroll
+    for (int k = i + 1; k < kM; ++k) v = __builtin_fma(-A[tri(k, i)], d[k], v);
+    d[i] = v;
+  }
+}
+
+__device__ __forceinline__ void targets(double ux, double uy, double T, double (&m)[kM]) {
+  const double E = 0.5 * (ux * ux + uy * uy + 2.0 * T);  // 2E = u^2 + D T, D = 2
+  m[0] = 1.0;
+  m[1] = ux;
+  m[2] = uy;
+  m[3] = ux * ux + T;
+  m[4] = ux * uy;
+  m[5] = uy * uy + T;
+  m[6] = 2.0 * ux * (E + T);
+  m[7] = 2.0 * uy * (E + T);
+}
+
 struct NewtonOut {
   int iters;  // residual evaluations, including the converged one
   bool ok;
 };
 
-// Solves for the weights at peculiar velocity (ux, uy) and temperature T.
-__device__ __forceinline__ NewtonOut solve_equilibrium(double ux, double uy, double T,
-                                                       double tol, int max_iter, Weights& w) {
+// Lattice-Maxwellian start (lambda_1 = -u/T, lambda_2 = I/(2T), the rest 0;
+// lambda_0 from the normalisation), FP64 exps throughout.  lam returns the
+// multipliers of the converged weights (before the final first-order step).
+__device__ __forceinline__ NewtonOut solve_robust(double ux, double uy, double T, double tol,
+                                                  int max_iter, Weights& w, double (&l)[kM]) {
   NewtonOut out{0, false};
-  const double E = 0.5 * (ux * ux + uy * uy + 2.0 * T);  // 2E = u^2 + D T, D = 2
-  const double m[kM] = {1.0,         ux, uy, ux * ux + T, ux * uy, uy * uy + T,
-                        2.0 * ux * (E + T), 2.0 * uy * (E + T)};
-  // initial guess: lattice-normalised Maxwellian (lambda_1 = -u/T,
-  // lambda_2 = I/(2T)); the normalisation is folded into the weights.
+  double m[kM];
+  targets(ux, uy, T, m);
   const double iT = 1.0 / T;
-  double l[kM] = {-1.0, -ux * iT, -uy * iT, 0.5 * iT, 0.0, 0.5 * iT, 0.0, 0.0};
+  l[0] = -1.0;
+  l[1] = -ux * iT;
+  l[2] = -uy * iT;
+  l[3] = 0.5 * iT;
+  l[4] = 0.0;
+  l[5] = 0.5 * iT;
+  l[6] = 0.0;
+  l[7] = 0.0;
   eval_weights(l, w);
   {
     double Z = w.w0;
@@ -113,87 +305,20 @@ __device__ __forceinline__ NewtonOut solve_equilibrium(double ux, double uy, dou
     l[0] = log(Z) - 1.0;
   }
   for (int it = 0; it < max_iter; ++it) {
-    double S[kPairs], D[kPairs];
-#pragma unroll
-    for (int p = 0; p < kPairs; ++p) {
-      S[p] = w.wp[p] + w.wm[p];
-      D[p] = w.wp[p] - w.wm[p];
-    }
-    const double w0 = w.w0;
-    const double M00 = mom<0, 0>(S, D, w0), M10 = mom<1, 0>(S, D, w0), M01 = mom<0, 1>(S, D, w0);
-    const double M20 = mom<2, 0>(S, D, w0), M11 = mom<1, 1>(S, D, w0), M02 = mom<0, 2>(S, D, w0);
-    const double M30 = mom<3, 0>(S, D, w0), M21 = mom<2, 1>(S, D, w0), M12 = mom<1, 2>(S, D, w0);
-    const double M03 = mom<0, 3>(S, D, w0);
-    double G[kM] = {M00 - m[0], M10 - m[1], M01 - m[2], M20 - m[3],
-                    M11 - m[4], M02 - m[5], M30 + M12 - m[6], M21 + M03 - m[7]};
-    double r = 0.0;
-#pragma unroll
-    for (int a = 0; a < kM; ++a) r = fmax(r, fabs(G[a]));
+    double S[kPairs], D[kPairs], G[kM], A[kTri], id[kM], d[kM];
+    LowMoments LM;
+    pair_sums(w, S, D);
+    const double r = residual(S, D, w.w0, m, LM, G);
     out.iters = it + 1;
-    if (!(r < 1e300)) return out;  // NaN or overflow
-    const double M40 = mom<4, 0>(S, D, w0), M31 = mom<3, 1>(S, D, w0), M22 = mom<2, 2>(S, D, w0);
-    const double M13 = mom<1, 3>(S, D, w0), M04 = mom<0, 4>(S, D, w0);
-    const double M50 = mom<5, 0>(S, D, w0), M41 = mom<4, 1>(S, D, w0), M32 = mom<3, 2>(S, D, w0);
-    const double M23 = mom<2, 3>(S, D, w0), M14 = mom<1, 4>(S, D, w0), M05 = mom<0, 5>(S, D, w0);
-    const double M60 = mom<6, 0>(S, D, w0), M51 = mom<5, 1>(S, D, w0), M42 = mom<4, 2>(S, D, w0);
-    const double M33 = mom<3, 3>(S, D, w0), M24 = mom<2, 4>(S, D, w0), M15 = mom<1, 5>(S, D, w0);
-    const double M06 = mom<0, 6>(S, D, w0);
-    // Hessian, lower triangle, basis (1, x, y, x2, xy, y2, x|xi|^2, y|xi|^2)
-    double H[kM][kM];
-    H[0][0] = M00;
-    H[1][0] = M10; H[1][1] = M20;
-    H[2][0] = M01; H[2][1] = M11; H[2][2] = M02;
-    H[3][0] = M20; H[3][1] = M30; H[3][2] = M21; H[3][3] = M40;
-    H[4][0] = M11; H[4][1] = M21; H[4][2] = M12; H[4][3] = M31; H[4][4] = M22;
-    H[5][0] = M02; H[5][1] = M12; H[5][2] = M03; H[5][3] = M22; H[5][4] = M13; H[5][5] = M04;
-    H[6][0] = M30 + M12; H[6][1] = M40 + M22; H[6][2] = M31 + M13; H[6][3] = M50 + M32;
-    H[6][4] = M41 + M23; H[6][5] = M32 + M14; H[6][6] = M60 + 2.0 * M42 + M24;
-    H[7][0] = M21 + M03; H[7][1] = M31 + M13; H[7][2] = M22 + M04; H[7][3] = M41 + M23;
-    H[7][4] = M32 + M14; H[7][5] = M23 + M05; H[7][6] = M51 + 2.0 * M33 + M15;
-    H[7][7] = M42 + 2.0 * M24 + M06;
-    // LDL^T: Ld[i][j] = L[i][j] d[j]
-    double L[kM][kM], Ld[kM][kM], id[kM];
-    bool spd = true;
-#pragma unroll
-    for (int j = 0; j < kM; ++j) {
-      double dj = H[j][j];
-#pragma unroll
-      for (int k = 0; k < j; ++k) dj -= L[j][k] * Ld[j][k];
-      spd = spd && (dj > 0.0);
-      id[j] = 1.0 / dj;
-#pragma unroll
-      for (int i = j + 1; i < kM; ++i) {
-        double v = H[i][j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) v -= L[i][k] * Ld[j][k];
-        Ld[i][j] = v;
-        L[i][j] = v * id[j];
-      }
-    }
-    if (!spd) return out;
-    double d[kM];
-#pragma unroll
-    for (int i = 0; i < kM; ++i) {
-      double v = G[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) v -= L[i][k] * d[k];
-      d[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < kM; ++i) d[i] *= id[i];
-#pragma unroll
-    for (int i = kM - 1; i >= 0; --i) {
-      double v = d[i];
-#pragma unroll
-      for (int k = i + 1; k < kM; ++k) v -= L[k][i] * d[k];
-      d[i] = v;
-    }
+    if (!(r < 1e300)) return out;
+    hessian(S, D, w.w0, LM, A);
+    if (!ldl_factor(A, id)) return out;
+    ldl_solve(A, id, G, d);
     if (r <= tol) {
       linear_update(d, w);
       out.ok = true;
       return out;
     }
-    // limit the step (max norm 1) far from the root
     double dmax = 0.0;
 #pragma unroll
     for (int a = 0; a < kM; ++a) dmax = fmax(dmax, fabs(d[a]));
@@ -201,6 +326,229 @@ __device__ __forceinline__ NewtonOut solve_equilibrium(double ux, double uy, dou
 #pragma unroll
     for (int a = 0; a < kM; ++a) l[a] = __builtin_fma(sc, d[a], l[a]);
     eval_weights(l, w);
+  }
+  return out;
+}
+
+// Geometry of the initial-guess table: dlambda = lambda - lambda_Maxwell
+// for lambda_1 .. lambda_7 (lambda_0 follows from the normalisation) on a
+// regular grid over a = |u_x|, b = |u_y| in [0, umax] and s = 1/T in
+// [smin, smax]; 8 floats per point (7 values and a validity slot that holds
+// NaN where the solve failed).
+struct GuessTable {
+  const float* data;  // [ns][nu][nu][8]
+  int nu, ns;
+  float umax, smin, smax, inv_hu, inv_hs;
+};
+
+// lambda guess at (ux, uy, T); returns false (and leaves the lattice
+// Maxwellian in l) when the state is outside the table.
+__device__ __forceinline__ bool table_guess(const GuessTable& tb, double ux, double uy, double iT,
+                                            double (&l)[kM]) {
+  l[0] = 0.0;
+  l[1] = -ux * iT;
+  l[2] = -uy * iT;
+  l[3] = 0.5 * iT;
+  l[4] = 0.0;
+  l[5] = 0.5 * iT;
+  l[6] = 0.0;
+  l[7] = 0.0;
+  const float a = fabsf(static_cast<float>(ux)), b = fabsf(static_cast<float>(uy));
+  const float s = static_cast<float>(iT);
+  if (!(a <= tb.umax && b <= tb.umax && s >= tb.smin && s <= tb.smax)) return false;
+  const float fa = a * tb.inv_hu, fb = b * tb.inv_hu, fs = (s - tb.smin) * tb.inv_hs;
+  const int ia = min(static_cast<int>(fa), tb.nu - 2);
+  const int ib = min(static_cast<int>(fb), tb.nu - 2);
+  const int is = min(static_cast<int>(fs), tb.ns - 2);
+  const float ta = fa - ia, tb_ = fb - ib, ts = fs - is;
+  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int da = c & 1, db = (c >> 1) & 1, ds = c >> 2;
+    const float wgt = (da ? ta : 1.0f - ta) * (db ? tb_ : 1.0f - tb_) * (ds ? ts : 1.0f - ts);
+    const float4* p = reinterpret_cast<const float4*>(
+        tb.data + (((static_cast<long>(is + ds) * tb.nu + (ib + db)) * tb.nu + (ia + da)) << 3));
+    const float4 v0 = p[0], v1 = p[1];
+    acc[0] = __builtin_fmaf(wgt, v0.x, acc[0]);
+    acc[1] = __builtin_fmaf(wgt, v0.y, acc[1]);
+    acc[2] = __builtin_fmaf(wgt, v0.z, acc[2]);
+    acc[3] = __builtin_fmaf(wgt, v0.w, acc[3]);
+    acc[4] = __builtin_fmaf(wgt, v1.x, acc[4]);
+    acc[5] = __builtin_fmaf(wgt, v1.y, acc[5]);
+    acc[6] = __builtin_fmaf(wgt, v1.z, acc[6]);
+    acc[7] = __builtin_fmaf(wgt, v1.w, acc[7]);
+  }
+  if (!(fabsf(acc[7]) < 1e30f)) return false;  // a corner failed to converge
+  // unfold the reflections u_x -> -u_x, u_y -> -u_y
+  const double sx = ux < 0.0 ? -1.0 : 1.0, sy = uy < 0.0 ? -1.0 : 1.0;
+  l[1] += sx * acc[0];
+  l[2] += sy * acc[1];
+  l[3] += acc[2];
+  l[4] += sx * sy * acc[3];
+  l[5] += acc[4];
+  l[6] += sx * acc[5];
+  l[7] += sy * acc[6];
+  return true;
+}
+
+// H accumulated directly from the weights, one +- pair at a time: the pair
+// adds phi_a(v) phi_b(v) (w+ + w- or w+ - w-, by the parity of phi_a phi_b).
+// Column 0 of H is sum_i w_i phi_a(xi_i), the constrained moments themselves.
+template <int p, int a, int b>
+__device__ __forceinline__ void hess_pair_entry(double (&A)[kTri], double S, double D) {
+  constexpr int x = kPX[p], y = kPY[p], s = x * x + y * y;
+  constexpr int phi[kM] = {1, x, y, x * x, x * y, y * y, x * s, y * s};
+  constexpr int par[kM] = {1, -1, -1, 1, 1, 1, -1, -1};  // phi(-v) = par * phi(v)
+  constexpr int c = phi[a] * phi[b];
+  if constexpr (par[a] * par[b] > 0)
+    A[tri(a, b)] = cmad<c>(A[tri(a, b)], S);
+  else
+    A[tri(a, b)] = cmad<c>(A[tri(a, b)], D);
+}
+
+template <int p, int idx = 0>
+__device__ __forceinline__ void hess_pair(double (&A)[kTri], double S, double D) {
+  if constexpr (idx < kTri) {
+    constexpr int a = [] { int r = 0; while ((r + 1) * (r + 2) / 2 <= idx) ++r; return r; }();
+    constexpr int b = idx - a * (a + 1) / 2;
+    hess_pair_entry<p, a, b>(A, S, D);
+    hess_pair<p, idx + 1>(A, S, D);
+  }
+}
+
+template <int p = 0>
+__device__ __forceinline__ void hessian_direct(const Weights& w, double (&A)[kTri]) {
+  if constexpr (p == 0) {
+#pragma unroll
+    for (int k = 0; k < kTri; ++k) A[k] = 0.0;
+    A[0] = w.w0;
+  }
+  if constexpr (p < kPairs) {
+    const double S = w.wp[p] + w.wm[p], D = w.wp[p] - w.wm[p];
+    hess_pair<p>(A, S, D);
+    hessian_direct<p + 1>(w, A);
+  }
+}
+
+// In-place LDL^T; on return the diagonal holds 1/D.
+__device__ __forceinline__ bool ldl_factor_inplace(double (&A)[kTri]) {
+  bool spd = true;
+#pragma unroll
+  for (int j = 0; j < kM; ++j) {
+    double t[kM];
+#pragma unroll
+    for (int k = 0; k < j; ++k) t[k] = A[tri(j, k)] * A[tri(k, k)];  // L_jk d_k
+    double dj = A[tri(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj = __builtin_fma(-A[tri(j, k)], t[k], dj);
+    spd = spd && (dj > 0.0);
+    const double idj = rcp64(dj);
+#pragma unroll
+    for (int i = j + 1; i < kM; ++i) {
+      double v = A[tri(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v = __builtin_fma(-A[tri(i, k)], t[k], v);
+      A[tri(i, j)] = v * idj;
+    }
+    A[tri(j, j)] = dj;
+  }
+#pragma unroll
+  for (int j = 0; j < kM; ++j) A[tri(j, j)] = rcp64(A[tri(j, j)]);
+  return spd;
+}
+
+// Solves in place: G holds the right-hand side on entry, the step on return.
+__device__ __forceinline__ void ldl_solve_inplace(const double (&A)[kTri], double (&G)[kM]) {
+#pragma unroll
+  for (int i = 0; i < kM; ++i) {
+#pragma unroll
+    for (int k = 0; k < i; ++k) G[i] = __builtin_fma(-A[tri(i, k)], G[k], G[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < kM; ++i) G[i] *= A[tri(i, i)];
+#pragma unroll
+  for (int i = kM - 1; i >= 0; --i) {
+#pragma unroll
+    for (int k = i + 1; k < kM; ++k) G[i] = __builtin_fma(-A[tri(k, i)], G[k], G[i]);
+  }
+}
+
+// w_i *= exp(-d . phi_i): polynomial when every |d . phi_i| < 0.03, FP64 exp otherwise.
+template <int p = 0>
+__device__ __forceinline__ void exp_update(const double (&d)[kM], Weights& w, bool small) {
+  if constexpr (p == 0) w.w0 *= small ? expm_small(d[0]) : exp(-d[0]);
+  if constexpr (p < kPairs) {
+    double e, o;
+    pair_exponent<p>(d, 0.0, e, o);
+    w.wp[p] *= small ? expm_small(e + o) : exp(-(e + o));
+    w.wm[p] *= small ? expm_small(e - o) : exp(-(e - o));
+    exp_update<p + 1>(d, w, small);
+  }
+}
+
+// Table start, FP32 exp for the first weights, then Newton steps applied to
+// the weights multiplicatively (no multipliers are carried); stops on
+// max |G| <= tol with a first-order final correction.
+__device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux, double uy,
+                                                double T, double tol, int max_iter, Weights& w) {
+  NewtonOut out{0, false};
+  {
+    // The first weights must be of exponential form to full FP64 accuracy:
+    // the multiplicative updates below never touch components outside the
+    // span of phi, so any noise introduced here would survive to the end.
+    double l[kM];
+    table_guess(tb, ux, uy, rcp64(T), l);
+    l[0] = -1.0;
+    eval_weights(l, w);
+  }
+  {
+    double Z = w.w0;
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) Z += w.wp[p] + w.wm[p];
+    if (!(Z < 1e300) || !(Z > 1e-300)) return out;
+    const double iZ = rcp64(Z);
+    w.w0 *= iZ;
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+      w.wp[p] *= iZ;
+      w.wm[p] *= iZ;
+    }
+  }
+  for (int it = 0; it < max_iter; ++it) {
+    double A[kTri], G[kM];
+    hessian_direct(w, A);
+    {
+      const double E = 0.5 * (ux * ux + uy * uy + 2.0 * T);
+      G[0] = A[tri(0, 0)] - 1.0;
+      G[1] = A[tri(1, 0)] - ux;
+      G[2] = A[tri(2, 0)] - uy;
+      G[3] = A[tri(3, 0)] - (ux * ux + T);
+      G[4] = A[tri(4, 0)] - ux * uy;
+      G[5] = A[tri(5, 0)] - (uy * uy + T);
+      G[6] = A[tri(6, 0)] - 2.0 * ux * (E + T);
+      G[7] = A[tri(7, 0)] - 2.0 * uy * (E + T);
+    }
+    double r = 0.0;
+#pragma unroll
+    for (int a = 0; a < kM; ++a) r = fmax(r, fabs(G[a]));
+    out.iters = it + 1;
+    if (!(r < 1e300)) return out;
+    if (!ldl_factor_inplace(A)) return out;
+    ldl_solve_inplace(A, G);  // G now holds the step
+    if (r <= tol) {
+      linear_update(G, w);
+      out.ok = true;
+      return out;
+    }
+    double dmax = 0.0;
+#pragma unroll
+    for (int a = 0; a < kM; ++a) dmax = fmax(dmax, fabs(G[a]));
+    if (dmax > 1.0) {
+      const double sc = 1.0 / dmax;
+#pragma unroll
+      for (int a = 0; a < kM; ++a) G[a] *= sc;
+    }
+    exp_update(G, w, max_step_exponent(G, 0.0) < 0.03);
   }
   return out;
 }

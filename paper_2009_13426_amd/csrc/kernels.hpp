@@ -24,6 +24,10 @@
 #ifndef LBM_HIST_BINS
 #define LBM_HIST_BINS 32
 #endif
+// Waves per SIMD the step kernel is compiled for (caps its registers).
+#ifndef LBM_STEP_WAVES_PER_EU
+#define LBM_STEP_WAVES_PER_EU 2
+#endif
 
 namespace lbm {
 
@@ -60,6 +64,7 @@ struct StepArgs {
   int* tout;
   Grid grid;
   Phys phys;
+  GuessTable table;
   int step;
   DevDiag* diag;
 };
@@ -76,6 +81,7 @@ struct InitArgs {
   int* tout;
   Grid grid;
   Phys phys;
+  GuessTable table;
   DevDiag* diag;
 };
 
@@ -207,7 +213,7 @@ __device__ __forceinline__ void node_uT(const S* f, const S* g, const int* tags,
 // source node s, rebuilt by Grad's ansatz from the moments and central
 // gradients at s (eq. GradGeneral with h* = h_eq + (1 - 1/tau) h_neq).
 template <typename S>
-__device__ __noinline__ unsigned rebuild_link(const StepArgs a, int s, int Lx, int Ly, int k,
+__device__ __forceinline__ unsigned rebuild_link(const StepArgs a, int s, int Lx, int Ly, int k,
                                               double& rf, double& rg, int& iters) {
   const S* f = static_cast<const S*>(a.fin);
   const S* g = static_cast<const S*>(a.gin);
@@ -242,7 +248,7 @@ __device__ __noinline__ unsigned rebuild_link(const StepArgs a, int s, int Lx, i
     dT[1] = 0.5 * (Tp - Tm);
   }
   Weights w;
-  const NewtonOut no = solve_equilibrium(ux - Lx, uy - Ly, T, P.tol, P.max_iter, w);
+  const NewtonOut no = solve_fast(a.table, ux - Lx, uy - Ly, T, P.tol, P.max_iter, w);
   iters = no.iters;
   if (!no.ok) return kCodeNewton;
   double wk = 0.0, cxk = 0.0, cyk = 0.0;
@@ -274,27 +280,33 @@ __device__ __forceinline__ double sensor_alpha(double eps) {
 }
 
 // ------------------------------------------------------------ fused step
-template <typename S, bool STREAM>
-__global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
-  __shared__ int sh_cnt[kWaves];
-  __shared__ int sh_src[kBlock];
-  __shared__ int sh_meta[kBlock];
-  __shared__ double sh_rf[kBlock];
-  __shared__ double sh_rg[kBlock];
+// One node per lane; BLOCK lanes per workgroup.  The pulled populations are
+// parked in LDS (plane-major, conflict-free) while the Newton solve holds
+// the registers, then read back for the collision.
+template <typename S, bool STREAM, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void step_kernel(StepArgs a) {
+  constexpr int WAVES = BLOCK / 64;
+  __shared__ S sh_pop[2 * kQ][BLOCK];
+  __shared__ int sh_cnt[WAVES];
+  __shared__ int sh_src[BLOCK];
+  __shared__ int sh_meta[BLOCK];
+  __shared__ double sh_rf[BLOCK];
+  __shared__ double sh_rg[BLOCK];
   __shared__ unsigned long long sh_stat[3 + LBM_HIST_BINS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const long long N = a.grid.N;
   const int nx = a.grid.nx, ny = a.grid.ny;
-  const long long n = static_cast<long long>(b) * kBlock + tid;
+  const long long n = static_cast<long long>(b) * BLOCK + tid;
   const bool active = n < N;
   const Phys& P = a.phys;
   const S* fin = static_cast<const S*>(a.fin);
   const S* gin = static_cast<const S*>(a.gin);
 
   if (P.stats) {
-    for (int i = tid; i < 3 + LBM_HIST_BINS; i += kBlock) sh_stat[i] = 0ull;
+    for (int i = tid; i < 3 + LBM_HIST_BINS; i += BLOCK) sh_stat[i] = 0ull;
     __syncthreads();
   }
 
@@ -310,36 +322,22 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
   const int uny = min(max(tag_uny(tag), -P.max_abs_shift), P.max_abs_shift);
   const int un16 = tag_un16(tag);
 
-  // a1: pull with mismatch test
-  S f[kQ], g[kQ];
+  // a1 (first half): which links have their source in another lattice
   unsigned mism = 0u;
-  if (active) {
-    static_for<0, kQ>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      if constexpr (STREAM) {
+  if constexpr (STREAM) {
+    if (active) {
+      static_for<0, kQ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
         const int sx = wrapc(x - (plane_cx(k) + unx), nx, a.grid.fast_x);
         const int sy = wrapc(y - (plane_cy(k) + uny), ny, a.grid.fast_y);
-        const long long s = static_cast<long long>(sy) * nx + sx;
-        if (tag_uc16(a.tin[s]) == un16) {
-          f[k] = fin[k * N + s];
-          g[k] = gin[k * N + s];
-        } else {
-          f[k] = S(0);
-          g[k] = S(0);
-          mism |= 1u << k;
-        }
-      } else {
-        f[k] = fin[k * N + n];
-        g[k] = gin[k * N + n];
-      }
-    });
-  }
+        if (tag_uc16(a.tin[static_cast<long long>(sy) * nx + sx]) != un16) mism |= 1u << k;
+      });
+    }
 
-  // a2: links whose source lives in another lattice, rebuilt by Grad's
-  // ansatz.  The block's (lane, link) items are packed and handed out one per
-  // lane, so a block pays ceil(items / 256) rebuild rounds instead of one per
-  // distinct link.
-  if constexpr (STREAM) {
+    // a2: those links are rebuilt by Grad's ansatz.  The block's
+    // (lane, link) items are packed and handed out one per lane, so a block
+    // pays ceil(items / BLOCK) rebuild rounds instead of one per distinct
+    // link; results go straight to the owner's LDS slots.
     const int cnt = __popc(mism);
     int v = cnt;
 #pragma unroll
@@ -351,20 +349,20 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     __syncthreads();
     int total = 0, wbase = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < WAVES; ++w) {
       const int c = sh_cnt[w];
       wbase += (w < wave) ? c : 0;
       total += c;
     }
     const int off = wbase + v - cnt;
-    for (int r0 = 0; r0 < total; r0 += kBlock) {
-      const bool mine = cnt > 0 && off < r0 + kBlock && off + cnt > r0;
+    for (int r0 = 0; r0 < total; r0 += BLOCK) {
+      const bool mine = cnt > 0 && off < r0 + BLOCK && off + cnt > r0;
       if (mine) {
         int j = off;
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
           if (mism & (1u << k)) {
-            if (j >= r0 && j < r0 + kBlock) {
+            if (j >= r0 && j < r0 + BLOCK) {
               const int sx = wrapc(x - (plane_cx(k) + unx), nx, a.grid.fast_x);
               const int sy = wrapc(y - (plane_cy(k) + uny), ny, a.grid.fast_y);
               sh_src[j - r0] = sy * nx + sx;
@@ -397,9 +395,9 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
           if (mism & (1u << k)) {
-            if (j >= r0 && j < r0 + kBlock) {
-              f[k] = static_cast<S>(sh_rf[j - r0]);
-              g[k] = static_cast<S>(sh_rg[j - r0]);
+            if (j >= r0 && j < r0 + BLOCK) {
+              sh_pop[k][tid] = static_cast<S>(sh_rf[j - r0]);
+              sh_pop[kQ + k][tid] = static_cast<S>(sh_rg[j - r0]);
             }
             ++j;
           }
@@ -410,18 +408,40 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
     if (P.stats && cnt) atomicAdd(&sh_stat[2], static_cast<unsigned long long>(cnt));
   }
 
+  // a1 (second half) and a3: pull the matching links into the LDS slots and
+  // take the moments in the frame of the node's lattice (eq. polyTemp)
+  double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
   if (active) {
-    // a3: moments in the frame of the node's lattice (eq. polyTemp)
-    double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
     static_for<0, kQ>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       constexpr int cx = plane_cx(k), cy = plane_cy(k);
-      const double fk = static_cast<double>(f[k]);
-      rho += fk;
-      jx = cmad<cx>(jx, fk);
-      jy = cmad<cy>(jy, fk);
-      e = cmad<cx * cx + cy * cy>(e, fk) + static_cast<double>(g[k]);
+      S fk, gk;
+      if (mism & (1u << k)) {
+        fk = sh_pop[k][tid];
+        gk = sh_pop[kQ + k][tid];
+      } else {
+        long long s = n;
+        if constexpr (STREAM) {
+          const int sx = wrapc(x - (cx + unx), nx, a.grid.fast_x);
+          const int sy = wrapc(y - (cy + uny), ny, a.grid.fast_y);
+          s = static_cast<long long>(sy) * nx + sx;
+        }
+        fk = fin[k * N + s];
+        gk = gin[k * N + s];
+        sh_pop[k][tid] = fk;
+        sh_pop[kQ + k][tid] = gk;
+      }
+      const double fd = static_cast<double>(fk);
+      rho += fd;
+      jx = cmad<cx>(jx, fd);
+      jy = cmad<cy>(jy, fd);
+      e = cmad<cx * cx + cy * cy>(e, fd) + static_cast<double>(gk);
     });
+  }
+  // the populations now live in LDS only; the solve gets the registers
+  asm volatile("" ::: "memory");
+
+  if (active) {
     const double upx = jx / rho, upy = jy / rho;
     const double T = (e - rho * (upx * upx + upy * upy)) / (2.0 * rho * P.Cv);
     unsigned code = 0;
@@ -443,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
         }
       }
       // a5: numerical equilibrium
-      const NewtonOut no = solve_equilibrium(upx, upy, T, P.tol, P.max_iter, w);
+      const NewtonOut no = solve_fast(a.table, upx, upy, T, P.tol, P.max_iter, w);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -458,8 +478,8 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
       record_failure(a.diag, a.step, n, code);
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        fout[k * N + n] = f[k];
-        gout[k * N + n] = g[k];
+        fout[k * N + n] = sh_pop[k][tid];
+        gout[k * N + n] = sh_pop[kQ + k][tid];
       });
     } else {
       // a6: collision, eq. (coll), with g_eq = (2 Cv - D) T f_eq (eq. gEq)
@@ -469,23 +489,24 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
           const double feq = rho * weight_of<k>(w);
-          eps += fabs(static_cast<double>(f[k]) - feq) / feq;
+          eps += fabs(static_cast<double>(sh_pop[k][tid]) - feq) * rcp64(feq);
         });
         tau *= sensor_alpha(eps * (1.0 / kQ));
       }
-      const double om = 1.0 / tau;
+      const double om = rcp64(tau);
       const double gfac = (2.0 * P.Cv - 2.0) * T;
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         const double feq = rho * weight_of<k>(w);
         const double geq = gfac * feq;
+        const S fk = sh_pop[k][tid], gk = sh_pop[kQ + k][tid];
         if constexpr (std::is_same<S, double>::value) {
-          fout[k * N + n] = __builtin_fma(om, feq - f[k], f[k]);
-          gout[k * N + n] = __builtin_fma(om, geq - g[k], g[k]);
+          fout[k * N + n] = __builtin_fma(om, feq - fk, fk);
+          gout[k * N + n] = __builtin_fma(om, geq - gk, gk);
         } else {
           const float omf = static_cast<float>(om);
-          fout[k * N + n] = __builtin_fmaf(omf, static_cast<float>(feq) - f[k], f[k]);
-          gout[k * N + n] = __builtin_fmaf(omf, static_cast<float>(geq) - g[k], g[k]);
+          fout[k * N + n] = __builtin_fmaf(omf, static_cast<float>(feq) - fk, fk);
+          gout[k * N + n] = __builtin_fmaf(omf, static_cast<float>(geq) - gk, gk);
         }
       });
     }
@@ -502,6 +523,43 @@ __global__ __launch_bounds__(kBlock) void step_kernel(StepArgs a) {
       atomicAdd(dst, sh_stat[tid]);
     }
   }
+}
+
+// Population storage type -> lanes per workgroup of the step kernel (the
+// LDS parking area is 42 x BLOCK values: 43 KB either way).
+template <typename S>
+constexpr int step_block() {
+  return std::is_same<S, double>::value ? 128 : 256;
+}
+
+// Builds the initial-guess table: one lane per grid point, Maxwellian-start
+// Newton in FP64, stores lambda_1..7 minus the lattice Maxwellian's.
+__global__ __launch_bounds__(256) void table_kernel(float* out, int nu, int ns, float umax,
+                                                    float smin, float smax, double tol,
+                                                    int max_iter) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nu * nu * ns) return;
+  const int ia = idx % nu, ib = (idx / nu) % nu, is = idx / (nu * nu);
+  const double a = umax * static_cast<double>(ia) / (nu - 1);
+  const double b = umax * static_cast<double>(ib) / (nu - 1);
+  const double s = smin + (smax - smin) * static_cast<double>(is) / (ns - 1);
+  const double T = 1.0 / s;
+  Weights w;
+  double l[kM];
+  const NewtonOut no = solve_robust(a, b, T, tol, max_iter, w, l);
+  float* o = out + 8l * idx;
+  if (!no.ok) {
+    for (int k = 0; k < 8; ++k) o[k] = __builtin_nanf("");
+    return;
+  }
+  o[0] = static_cast<float>(l[1] + a * s);  // lambda_1x - (-u_x / T)
+  o[1] = static_cast<float>(l[2] + b * s);
+  o[2] = static_cast<float>(l[3] - 0.5 * s);
+  o[3] = static_cast<float>(l[4]);
+  o[4] = static_cast<float>(l[5] - 0.5 * s);
+  o[5] = static_cast<float>(l[6]);
+  o[6] = static_cast<float>(l[7]);
+  o[7] = 1.0f;
 }
 
 // ------------------------------------------------------------ init
@@ -537,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a) {
   a.tout[n] = tag_pack(Ux, Uy, Ux, Uy);
   Weights w;
   if (!code) {
-    const NewtonOut no = solve_equilibrium(ux - Ux, uy - Uy, T, P.tol, P.max_iter, w);
+    const NewtonOut no = solve_fast(a.table, ux - Ux, uy - Uy, T, P.tol, P.max_iter, w);
     if (!no.ok) code = kCodeNewton;
   }
   if (code) {

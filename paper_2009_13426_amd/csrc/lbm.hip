@@ -23,12 +23,20 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
+// Initial-guess table: |u'| in [0, 1] (step 1/32), 1/T in [0.5, 1/0.3]
+// (35 levels), 8 floats per point.
+constexpr int kTabU = 33;
+constexpr int kTabS = 35;
+constexpr float kTabUmax = 1.0f;
+constexpr float kTabSmin = 0.5f;
+constexpr float kTabSmax = 1.0f / 0.3f;
+
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
   size_t pop_bytes;  // one buffer: f and g, 21 planes each
   size_t tag_bytes;
-  size_t diag_off, part_off, sums_off, total;
+  size_t diag_off, part_off, sums_off, table_off, total;
   size_t off_pop[2], off_tag[2];
   int nparts;
 };
@@ -67,6 +75,8 @@ Layout layout(const lbm_config* c) {
   off += align_up(static_cast<size_t>(L.nparts) * 4 * sizeof(double));
   L.sums_off = off;
   off += align_up(4 * sizeof(double));
+  L.table_off = off;
+  off += align_up(static_cast<size_t>(kTabU) * kTabU * kTabS * 8 * sizeof(float));
   L.total = off;
   return L;
 }
@@ -84,7 +94,9 @@ struct lbm_ctx {
   int64_t steps_done;
   Grid grid;
   Phys phys;
-  int nblocks;
+  GuessTable table;
+  int nblocks;       // 256-lane blocks (init, exports, reductions)
+  int step_blocks;   // blocks of the step kernel
 
   void* f(int b) const { return ws + lay.off_pop[b]; }
   void* g(int b) const {
@@ -122,19 +134,22 @@ lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step)
   a.tout = c->tag(dst);
   a.grid = c->grid;
   a.phys = c->phys;
+  a.table = c->table;
   a.step = step;
   a.diag = c->diag();
-  const dim3 grid(c->nblocks), block(kBlock);
+  const dim3 grid(c->step_blocks);
   if (c->cfg.precision == LBM_FP64) {
+    constexpr int B = step_block<double>();
     if (stream_pass)
-      hipLaunchKernelGGL((step_kernel<double, true>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_kernel<double, true, B>), grid, dim3(B), 0, c->stream, a);
     else
-      hipLaunchKernelGGL((step_kernel<double, false>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_kernel<double, false, B>), grid, dim3(B), 0, c->stream, a);
   } else {
+    constexpr int B = step_block<float>();
     if (stream_pass)
-      hipLaunchKernelGGL((step_kernel<float, true>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_kernel<float, true, B>), grid, dim3(B), 0, c->stream, a);
     else
-      hipLaunchKernelGGL((step_kernel<float, false>), grid, block, 0, c->stream, a);
+      hipLaunchKernelGGL((step_kernel<float, false, B>), grid, dim3(B), 0, c->stream, a);
   }
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
 }
@@ -166,6 +181,7 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
   a.tout = c->tag(0);
   a.grid = c->grid;
   a.phys = c->phys;
+  a.table = c->table;
   a.diag = c->diag();
   if (c->cfg.precision == LBM_FP64)
     hipLaunchKernelGGL(init_kernel<double>, dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
@@ -248,7 +264,25 @@ lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* strea
   c->phys.sensor = cfg->sensor;
   c->phys.stats = cfg->collect_stats;
   c->nblocks = L.nparts;
+  {
+    const int B = cfg->precision == LBM_FP64 ? step_block<double>() : step_block<float>();
+    c->step_blocks = static_cast<int>((c->grid.N + B - 1) / B);
+  }
+  c->table.data = reinterpret_cast<const float*>(c->ws + L.table_off);
+  c->table.nu = kTabU;
+  c->table.ns = kTabS;
+  c->table.umax = kTabUmax;
+  c->table.smin = kTabSmin;
+  c->table.smax = kTabSmax;
+  c->table.inv_hu = (kTabU - 1) / kTabUmax;
+  c->table.inv_hs = (kTabS - 1) / (kTabSmax - kTabSmin);
   hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag());
+  {
+    const int pts = kTabU * kTabU * kTabS;
+    hipLaunchKernelGGL(table_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream,
+                       reinterpret_cast<float*>(c->ws + L.table_off), kTabU, kTabS, kTabUmax,
+                       kTabSmin, kTabSmax, 1e-13, 100);
+  }
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
     return LBM_ERR_HIP;
