@@ -67,7 +67,7 @@ typedef enum {
 } lbm_shift_mode;
 
 typedef struct {
-  int32_t nx, ny;            /* grid; both >= 1, nx * ny < 2^31 */
+  int32_t nx, ny;            /* grid; both >= 1, nx * ny * (8 or 4 bytes) < 2^32 */
   int32_t precision;         /* lbm_precision */
   double gamma;              /* heat capacity ratio; Cv = 1/(gamma-1), Cp = gamma Cv */
   double nu;                 /* kinematic viscosity >= 0 (lattice units) */

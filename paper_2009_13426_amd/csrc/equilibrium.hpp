@@ -355,32 +355,44 @@ __device__ __forceinline__ bool table_guess(const GuessTable& tb, double ux, dou
   l[7] = 0.0;
   const float a = fabsf(static_cast<float>(ux)), b = fabsf(static_cast<float>(uy));
   const float s = static_cast<float>(iT);
-  if (!(a <= tb.umax && b <= tb.umax && s >= tb.smin && s <= tb.smax)) return false;
-  const float fa = a * tb.inv_hu, fb = b * tb.inv_hu, fs = (s - tb.smin) * tb.inv_hs;
+  const bool inside = a <= tb.umax && b <= tb.umax && s >= tb.smin && s <= tb.smax;
+  // clamped cell index: every corner read stays inside the table
+  const float fa = fminf(a, tb.umax) * tb.inv_hu, fb = fminf(b, tb.umax) * tb.inv_hu;
+  const float fs = (fminf(fmaxf(s, tb.smin), tb.smax) - tb.smin) * tb.inv_hs;
   const int ia = min(static_cast<int>(fa), tb.nu - 2);
   const int ib = min(static_cast<int>(fb), tb.nu - 2);
   const int is = min(static_cast<int>(fs), tb.ns - 2);
   const float ta = fa - ia, tb_ = fb - ib, ts = fs - is;
+  // all sixteen loads in flight before the first is used
+  float4 v[8][2];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int da = c & 1, db = (c >> 1) & 1, ds = c >> 2;
+    const float4* p = reinterpret_cast<const float4*>(
+        tb.data + (((static_cast<long>(is + ds) * tb.nu + (ib + db)) * tb.nu + (ia + da)) << 3));
+    v[c][0] = p[0];
+    v[c][1] = p[1];
+  }
   float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int da = c & 1, db = (c >> 1) & 1, ds = c >> 2;
     const float wgt = (da ? ta : 1.0f - ta) * (db ? tb_ : 1.0f - tb_) * (ds ? ts : 1.0f - ts);
-    const float4* p = reinterpret_cast<const float4*>(
-        tb.data + (((static_cast<long>(is + ds) * tb.nu + (ib + db)) * tb.nu + (ia + da)) << 3));
-    const float4 v0 = p[0], v1 = p[1];
-    acc[0] = __builtin_fmaf(wgt, v0.x, acc[0]);
-    acc[1] = __builtin_fmaf(wgt, v0.y, acc[1]);
-    acc[2] = __builtin_fmaf(wgt, v0.z, acc[2]);
-    acc[3] = __builtin_fmaf(wgt, v0.w, acc[3]);
-    acc[4] = __builtin_fmaf(wgt, v1.x, acc[4]);
-    acc[5] = __builtin_fmaf(wgt, v1.y, acc[5]);
-    acc[6] = __builtin_fmaf(wgt, v1.z, acc[6]);
-    acc[7] = __builtin_fmaf(wgt, v1.w, acc[7]);
+    acc[0] = __builtin_fmaf(wgt, v[c][0].x, acc[0]);
+    acc[1] = __builtin_fmaf(wgt, v[c][0].y, acc[1]);
+    acc[2] = __builtin_fmaf(wgt, v[c][0].z, acc[2]);
+    acc[3] = __builtin_fmaf(wgt, v[c][0].w, acc[3]);
+    acc[4] = __builtin_fmaf(wgt, v[c][1].x, acc[4]);
+    acc[5] = __builtin_fmaf(wgt, v[c][1].y, acc[5]);
+    acc[6] = __builtin_fmaf(wgt, v[c][1].z, acc[6]);
+    acc[7] = __builtin_fmaf(wgt, v[c][1].w, acc[7]);
   }
-  if (!(fabsf(acc[7]) < 1e30f)) return false;  // a corner failed to converge
-  // unfold the reflections u_x -> -u_x, u_y -> -u_y
+  // outside the table, or a corner that failed to converge: Maxwellian start
+  const bool ok = inside && fabsf(acc[7]) < 1e30f;
   const double sx = ux < 0.0 ? -1.0 : 1.0, sy = uy < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) acc[k] = ok ? acc[k] : 0.0f;
+  // unfold the reflections u_x -> -u_x, u_y -> -u_y
   l[1] += sx * acc[0];
   l[2] += sy * acc[1];
   l[3] += acc[2];
@@ -388,7 +400,7 @@ __device__ __forceinline__ bool table_guess(const GuessTable& tb, double ux, dou
   l[5] += acc[4];
   l[6] += sx * acc[5];
   l[7] += sy * acc[6];
-  return true;
+  return ok;
 }
 
 // H accumulated directly from the weights, one +- pair at a time: the pair

@@ -104,6 +104,20 @@ __device__ __forceinline__ int wrapc(int v, int n, int fast) {
   return v < 0 ? v + n : v;
 }
 
+// Element idx of one population plane, addressed by a 32-bit byte offset
+// from the plane's (wave-uniform) base; the host admits only grids whose
+// planes are below 4 GiB.
+template <typename S>
+__device__ __forceinline__ const S& plane_at(const S* plane, unsigned idx) {
+  return *reinterpret_cast<const S*>(reinterpret_cast<const char*>(plane) +
+                                     idx * static_cast<unsigned>(sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ S& plane_at(S* plane, unsigned idx) {
+  return *reinterpret_cast<S*>(reinterpret_cast<char*>(plane) +
+                               idx * static_cast<unsigned>(sizeof(S)));
+}
+
 // Consecutive blocks are dispatched round-robin over the 8 XCDs; remap so
 // that each XCD (own L2) works on one contiguous range of nodes.
 __device__ __forceinline__ int xcd_remap(int b, int G) {
@@ -134,17 +148,24 @@ __device__ __forceinline__ double weight_of(const Weights& w) {
     return w.wm[(k - 1) >> 1];
 }
 
-// Moments of one node's stored populations in its own lattice frame.
+// Moments of one node's stored populations in its own lattice frame (all
+// 42 loads issued before the first is used).
 template <typename S>
 __device__ __forceinline__ void node_moments(const S* f, const S* g, long long N, long long s,
                                              double& rho, double& upx, double& upy, double& T,
                                              double Cv) {
+  S fv[kQ], gv[kQ];
+  static_for<0, kQ>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    fv[k] = plane_at(f + k * N, static_cast<unsigned>(s));
+    gv[k] = plane_at(g + k * N, static_cast<unsigned>(s));
+  });
   double r = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
   static_for<0, kQ>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
     constexpr int cx = plane_cx(k), cy = plane_cy(k);
-    const double fk = static_cast<double>(f[k * N + s]);
-    const double gk = static_cast<double>(g[k * N + s]);
+    const double fk = static_cast<double>(fv[k]);
+    const double gk = static_cast<double>(gv[k]);
     r += fk;
     jx = cmad<cx>(jx, fk);
     jy = cmad<cy>(jy, fk);
@@ -322,15 +343,36 @@ void step_kernel(StepArgs a) {
   const int uny = min(max(tag_uny(tag), -P.max_abs_shift), P.max_abs_shift);
   const int un16 = tag_un16(tag);
 
+  // Source node of link k is (x - cx - Ux, y - cy - Uy): with cx, cy in
+  // [-3, 3] the wrapped columns and row offsets take seven values each.
+  int col[7], row[7];
+  if constexpr (STREAM) {
+    static_for<0, 7>([&](auto ic) {
+      constexpr int c = decltype(ic)::value - 3;
+      col[c + 3] = wrapc(x - (c + unx), nx, a.grid.fast_x);
+      row[c + 3] = wrapc(y - (c + uny), ny, a.grid.fast_y) * nx;
+    });
+  }
+  auto source = [&](auto kc) -> unsigned {
+    constexpr int k = decltype(kc)::value;
+    if constexpr (STREAM)
+      return static_cast<unsigned>(row[plane_cy(k) + 3] + col[plane_cx(k) + 3]);
+    else
+      return static_cast<unsigned>(n);
+  };
+
   // a1 (first half): which links have their source in another lattice
   unsigned mism = 0u;
   if constexpr (STREAM) {
     if (active) {
+      int st[kQ];
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const int sx = wrapc(x - (plane_cx(k) + unx), nx, a.grid.fast_x);
-        const int sy = wrapc(y - (plane_cy(k) + uny), ny, a.grid.fast_y);
-        if (tag_uc16(a.tin[static_cast<long long>(sy) * nx + sx]) != un16) mism |= 1u << k;
+        st[k] = plane_at(a.tin, source(kc));
+      });
+      static_for<0, kQ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (tag_uc16(st[k]) != un16) mism |= 1u << k;
       });
     }
 
@@ -363,9 +405,7 @@ void step_kernel(StepArgs a) {
           constexpr int k = decltype(kc)::value;
           if (mism & (1u << k)) {
             if (j >= r0 && j < r0 + BLOCK) {
-              const int sx = wrapc(x - (plane_cx(k) + unx), nx, a.grid.fast_x);
-              const int sy = wrapc(y - (plane_cy(k) + uny), ny, a.grid.fast_y);
-              sh_src[j - r0] = sy * nx + sx;
+              sh_src[j - r0] = static_cast<int>(source(kc));
               sh_meta[j - r0] = k | ((unx & 0xFF) << 8) | ((uny & 0xFF) << 16);
             }
             ++j;
@@ -408,29 +448,31 @@ void step_kernel(StepArgs a) {
     if (P.stats && cnt) atomicAdd(&sh_stat[2], static_cast<unsigned long long>(cnt));
   }
 
-  // a1 (second half) and a3: pull the matching links into the LDS slots and
-  // take the moments in the frame of the node's lattice (eq. polyTemp)
+  // a1 (second half) and a3: every link is loaded (all loads in flight at
+  // once), rebuilt links then replace theirs from LDS by a select; the
+  // merged populations are parked in LDS and their moments taken in the
+  // frame of the node's lattice (eq. polyTemp)
   double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
   if (active) {
+    S fv[kQ], gv[kQ];
+    static_for<0, kQ>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const unsigned s = source(kc);
+      fv[k] = plane_at(fin + k * N, s);
+      gv[k] = plane_at(gin + k * N, s);
+    });
     static_for<0, kQ>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       constexpr int cx = plane_cx(k), cy = plane_cy(k);
-      S fk, gk;
-      if (mism & (1u << k)) {
-        fk = sh_pop[k][tid];
-        gk = sh_pop[kQ + k][tid];
-      } else {
-        long long s = n;
-        if constexpr (STREAM) {
-          const int sx = wrapc(x - (cx + unx), nx, a.grid.fast_x);
-          const int sy = wrapc(y - (cy + uny), ny, a.grid.fast_y);
-          s = static_cast<long long>(sy) * nx + sx;
-        }
-        fk = fin[k * N + s];
-        gk = gin[k * N + s];
-        sh_pop[k][tid] = fk;
-        sh_pop[kQ + k][tid] = gk;
+      S fk = fv[k], gk = gv[k];
+      if constexpr (STREAM) {
+        const bool m = (mism >> k) & 1u;
+        const S rf = sh_pop[k][tid], rg = sh_pop[kQ + k][tid];
+        fk = m ? rf : fk;
+        gk = m ? rg : gk;
       }
+      sh_pop[k][tid] = fk;
+      sh_pop[kQ + k][tid] = gk;
       const double fd = static_cast<double>(fk);
       rho += fd;
       jx = cmad<cx>(jx, fd);
@@ -478,8 +520,8 @@ void step_kernel(StepArgs a) {
       record_failure(a.diag, a.step, n, code);
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        fout[k * N + n] = sh_pop[k][tid];
-        gout[k * N + n] = sh_pop[kQ + k][tid];
+        plane_at(fout + k * N, static_cast<unsigned>(n)) = sh_pop[k][tid];
+        plane_at(gout + k * N, static_cast<unsigned>(n)) = sh_pop[kQ + k][tid];
       });
     } else {
       // a6: collision, eq. (coll), with g_eq = (2 Cv - D) T f_eq (eq. gEq)
@@ -501,12 +543,12 @@ void step_kernel(StepArgs a) {
         const double geq = gfac * feq;
         const S fk = sh_pop[k][tid], gk = sh_pop[kQ + k][tid];
         if constexpr (std::is_same<S, double>::value) {
-          fout[k * N + n] = __builtin_fma(om, feq - fk, fk);
-          gout[k * N + n] = __builtin_fma(om, geq - gk, gk);
+          plane_at(fout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, feq - fk, fk);
+          plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, geq - gk, gk);
         } else {
           const float omf = static_cast<float>(om);
-          fout[k * N + n] = __builtin_fmaf(omf, static_cast<float>(feq) - fk, fk);
-          gout[k * N + n] = __builtin_fmaf(omf, static_cast<float>(geq) - gk, gk);
+          plane_at(fout + k * N, static_cast<unsigned>(n)) = __builtin_fmaf(omf, static_cast<float>(feq) - fk, fk);
+          plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fmaf(omf, static_cast<float>(geq) - gk, gk);
         }
       });
     }

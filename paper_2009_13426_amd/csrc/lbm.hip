@@ -44,7 +44,8 @@ struct Layout {
 bool config_ok(const lbm_config* c) {
   if (!c) return false;
   const long long N = static_cast<long long>(c->nx) * c->ny;
-  return c->nx >= 1 && c->ny >= 1 && N < (1ll << 31) &&
+  const long long es = c->precision == LBM_FP64 ? 8 : 4;
+  return c->nx >= 1 && c->ny >= 1 && N < (1ll << 31) && N * es < (1ll << 32) &&
          (c->precision == LBM_FP64 || c->precision == LBM_FP32_STORE) && c->gamma > 1.0 &&
          std::isfinite(c->gamma) && c->nu >= 0.0 && std::isfinite(c->nu) &&
          c->shift_mode >= 0 && c->shift_mode <= 2 && c->shift_halfwidth >= 0.5 &&
