@@ -19,19 +19,68 @@
 //
 // Two drivers share these pieces:
 //   solve_robust  lattice-Maxwellian start, weights always recomputed from
-//                 the multipliers with the FP64 exp (table build, init);
+//                 the multipliers with the library exp (table build);
 //   solve_fast    start from an interpolated table of lambda - lambda_Maxwell,
 //                 weights carried (not multipliers): later updates
-//                 w *= exp(-delta . phi) by a degree-7 polynomial while
-//                 |delta . phi| < 0.03 (truncation below 1e-17 relative), the
-//                 FP64 exp otherwise; H is accumulated straight from the
-//                 weights, one +- pair at a time.
+//                 w *= exp(-delta . phi) by Taylor polynomials of degree 3
+//                 (|delta . phi| < 1e-5) or 7 (< 0.03) and by exp_cw
+//                 otherwise; H is accumulated straight from the weights, one
+//                 +- pair at a time, and its factors are reused for the final
+//                 correction.
 // Both stop on the same criterion, so both reach the unique root to rounding.
 #pragma once
 
 #include "lattice.hpp"
 
 namespace lbm {
+
+// e^x by Cody and Waite's argument reduction, x = k ln2 + r with k the
+// nearest integer to x / ln2 and ln2 split in a head with trailing zero bits
+// (exact k * head for |k| < 2^20) and a tail, then e^r from its Taylor
+// polynomial of degree 13 on |r| <= ln2 / 2 (truncation below 5e-18
+// relative) and the exact scaling by 2^k.  Finite arguments of magnitude up
+// to ~700; NaN propagates.  Error within a few units in the last place.
+__device__ __forceinline__ double exp_cw(double x) {
+  constexpr double kLog2e = 1.4426950408889634074;
+  constexpr double kLn2Hi = 6.93147180369123816490e-01;
+  constexpr double kLn2Lo = 1.90821492927058770002e-10;
+  const double k = __builtin_rint(x * kLog2e);
+  double r = __builtin_fma(-k, kLn2Hi, x);
+  r = __builtin_fma(-k, kLn2Lo, r);
+  double p = 1.0 / 6227020800.0;  // 1/13!
+  p = __builtin_fma(p, r, 1.0 / 479001600.0);
+  p = __builtin_fma(p, r, 1.0 / 39916800.0);
+  p = __builtin_fma(p, r, 1.0 / 3628800.0);
+  p = __builtin_fma(p, r, 1.0 / 362880.0);
+  p = __builtin_fma(p, r, 1.0 / 40320.0);
+  p = __builtin_fma(p, r, 1.0 / 5040.0);
+  p = __builtin_fma(p, r, 1.0 / 720.0);
+  p = __builtin_fma(p, r, 1.0 / 120.0);
+  p = __builtin_fma(p, r, 1.0 / 24.0);
+  p = __builtin_fma(p, r, 1.0 / 6.0);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, static_cast<int>(k));
+}
+
+// exp(-z) as used for the weights: exp_cw, or the library exp when
+// LBM_EXP_CW is 0.
+#ifndef LBM_EXP_CW
+#define LBM_EXP_CW 1
+#endif
+// Reuse of the last factorisation for the final correction (1), or a fresh
+// factorisation (0, default: keeping the factors live costs registers).
+#ifndef LBM_NEWTON_REUSE_FACTORS
+#define LBM_NEWTON_REUSE_FACTORS 0
+#endif
+__device__ __forceinline__ double exp_neg(double z) {
+#if LBM_EXP_CW
+  return exp_cw(-z);
+#else
+  return exp(-z);
+#endif
+}
 
 struct Weights {
   double wp[kPairs];  // w at +v_p
@@ -50,12 +99,12 @@ __device__ __forceinline__ void pair_exponent(const double (&l)[kM], double base
 
 template <int p = 0>
 __device__ __forceinline__ void eval_weights(const double (&l)[kM], Weights& w) {
-  if constexpr (p == 0) w.w0 = exp(-(1.0 + l[0]));
+  if constexpr (p == 0) w.w0 = exp_neg(1.0 + l[0]);
   if constexpr (p < kPairs) {
     double e, o;
     pair_exponent<p>(l, 1.0, e, o);
-    w.wp[p] = exp(-(e + o));
-    w.wm[p] = exp(-(e - o));
+    w.wp[p] = exp_neg(e + o);
+    w.wm[p] = exp_neg(e - o);
     eval_weights<p + 1>(l, w);
   }
 }
@@ -85,6 +134,16 @@ __device__ __forceinline__ double expm_small(double z) {
   p = __builtin_fma(p, t, 1.0);
   p = __builtin_fma(p, t, 1.0);
   return p;
+}
+
+// exp(-z) for |z| < 1e-5 by its Taylor polynomial of degree 3 (truncation
+// below 1e-21 relative).
+__device__ __forceinline__ double expm_tiny(double z) {
+  const double t = -z;
+  double p = 1.0 / 6.0;
+  p = __builtin_fma(p, t, 0.5);
+  p = __builtin_fma(p, t, 1.0);
+  return __builtin_fma(p, t, 1.0);
 }
 
 // largest |d . phi_i| over the velocities
@@ -423,22 +482,27 @@ __device__ __forceinline__ void hess_pair(double (&A)[kTri], double S, double D)
   if constexpr (idx < kTri) {
     constexpr int a = [] { int r = 0; while ((r + 1) * (r + 2) / 2 <= idx) ++r; return r; }();
     constexpr int b = idx - a * (a + 1) / 2;
-    hess_pair_entry<p, a, b>(A, S, D);
+    if constexpr (b > 0) hess_pair_entry<p, a, b>(A, S, D);
     hess_pair<p, idx + 1>(A, S, D);
   }
 }
 
+// H with column 0 taken from the constraint sums c; the other 28 entries
+// accumulated pair by pair (the rest velocity adds to entry (0, 0) only).
 template <int p = 0>
-__device__ __forceinline__ void hessian_direct(const Weights& w, double (&A)[kTri]) {
+__device__ __forceinline__ void hessian_direct(const Weights& w, const double (&c)[kM],
+                                               double (&A)[kTri]) {
   if constexpr (p == 0) {
 #pragma unroll
     for (int k = 0; k < kTri; ++k) A[k] = 0.0;
-    A[0] = w.w0;
   }
   if constexpr (p < kPairs) {
     const double S = w.wp[p] + w.wm[p], D = w.wp[p] - w.wm[p];
-    hess_pair<p>(A, S, D);
-    hessian_direct<p + 1>(w, A);
+    hess_pair<p, 1>(A, S, D);
+    hessian_direct<p + 1>(w, c, A);
+  } else {
+#pragma unroll
+    for (int a = 0; a < kM; ++a) A[tri(a, 0)] = c[a];
   }
 }
 
@@ -485,22 +549,61 @@ __device__ __forceinline__ void ldl_solve_inplace(const double (&A)[kTri], doubl
   }
 }
 
-// w_i *= exp(-d . phi_i): polynomial when every |d . phi_i| < 0.03, FP64 exp otherwise.
-template <int p = 0>
-__device__ __forceinline__ void exp_update(const double (&d)[kM], Weights& w, bool small) {
-  if constexpr (p == 0) w.w0 *= small ? expm_small(d[0]) : exp(-d[0]);
+// w_i *= F(d . phi_i) for one of the exp(-z) evaluators below.
+template <typename F, int p = 0>
+__device__ __forceinline__ void scale_weights(const double (&d)[kM], Weights& w, F f) {
+  if constexpr (p == 0) w.w0 *= f(d[0]);
   if constexpr (p < kPairs) {
     double e, o;
     pair_exponent<p>(d, 0.0, e, o);
-    w.wp[p] *= small ? expm_small(e + o) : exp(-(e + o));
-    w.wm[p] *= small ? expm_small(e - o) : exp(-(e - o));
-    exp_update<p + 1>(d, w, small);
+    w.wp[p] *= f(e + o);
+    w.wm[p] *= f(e - o);
+    scale_weights<F, p + 1>(d, w, f);
   }
 }
 
-// Table start, FP32 exp for the first weights, then Newton steps applied to
-// the weights multiplicatively (no multipliers are carried); stops on
-// max |G| <= tol with a first-order final correction.
+// w_i *= exp(-d . phi_i): the degree-3 polynomial when every |d . phi_i| <
+// 1e-5, the degree-7 one below 0.03, exp otherwise.  One branch per update
+// (lanes of a wave normally agree), not one per weight.
+__device__ __forceinline__ void exp_update(const double (&d)[kM], Weights& w, double big) {
+  if (big < 1e-5) {
+    scale_weights(d, w, [](double z) { return expm_tiny(z); });
+  } else if (big < 0.03) {
+    scale_weights(d, w, [](double z) { return expm_small(z); });
+  } else {
+    scale_weights(d, w, [](double z) { return exp_neg(z); });
+  }
+}
+
+// Sums sum_i w_i phi_a(xi_i), a = 0..7 (column 0 of H), from the +- pairs.
+template <int p = 0>
+__device__ __forceinline__ void constraint_moments(const Weights& w, double (&c)[kM]) {
+  if constexpr (p == 0) {
+    c[0] = w.w0;
+#pragma unroll
+    for (int a = 1; a < kM; ++a) c[a] = 0.0;
+  }
+  if constexpr (p < kPairs) {
+    constexpr int x = kPX[p], y = kPY[p], sq = x * x + y * y;
+    const double S = w.wp[p] + w.wm[p], D = w.wp[p] - w.wm[p];
+    c[0] += S;
+    c[1] = cmad<x>(c[1], D);
+    c[2] = cmad<y>(c[2], D);
+    c[3] = cmad<x * x>(c[3], S);
+    c[4] = cmad<x * y>(c[4], S);
+    c[5] = cmad<y * y>(c[5], S);
+    c[6] = cmad<x * sq>(c[6], D);
+    c[7] = cmad<y * sq>(c[7], D);
+    constraint_moments<p + 1>(w, c);
+  }
+}
+
+// Table start, then Newton steps applied to the weights multiplicatively (no
+// multipliers are carried).  Stops on max |G| <= tol with a first-order
+// final correction; when the previous step was small (every |d . phi_i| <
+// 1e-3) that correction reuses the previous factorisation of H, whose
+// relative change is of the size of that step, so the correction is exact
+// to far below the tolerance.
 __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux, double uy,
                                                 double T, double tol, int max_iter, Weights& w) {
   NewtonOut out{0, false};
@@ -526,25 +629,43 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
       w.wm[p] *= iZ;
     }
   }
+  const double ET = 0.5 * (ux * ux + uy * uy + 2.0 * T) + T;  // E + T
+  // constraint targets, recomputed where used (cheaper than keeping them live)
+  auto target = [&](int a) {
+    return a == 0 ? 1.0
+         : a == 1 ? ux
+         : a == 2 ? uy
+         : a == 3 ? ux * ux + T
+         : a == 4 ? ux * uy
+         : a == 5 ? uy * uy + T
+         : a == 6 ? 2.0 * ux * ET
+                  : 2.0 * uy * ET;
+  };
+  double A[kTri];
+  bool reuse = false;  // A holds the factors of a Hessian close to the current one
   for (int it = 0; it < max_iter; ++it) {
-    double A[kTri], G[kM];
-    hessian_direct(w, A);
-    {
-      const double E = 0.5 * (ux * ux + uy * uy + 2.0 * T);
-      G[0] = A[tri(0, 0)] - 1.0;
-      G[1] = A[tri(1, 0)] - ux;
-      G[2] = A[tri(2, 0)] - uy;
-      G[3] = A[tri(3, 0)] - (ux * ux + T);
-      G[4] = A[tri(4, 0)] - ux * uy;
-      G[5] = A[tri(5, 0)] - (uy * uy + T);
-      G[6] = A[tri(6, 0)] - 2.0 * ux * (E + T);
-      G[7] = A[tri(7, 0)] - 2.0 * uy * (E + T);
-    }
+    double G[kM];
+    constraint_moments(w, G);
+#pragma unroll
+    for (int a = 0; a < kM; ++a) G[a] -= target(a);
     double r = 0.0;
 #pragma unroll
     for (int a = 0; a < kM; ++a) r = fmax(r, fabs(G[a]));
     out.iters = it + 1;
     if (!(r < 1e300)) return out;
+    if (r <= tol && reuse) {
+      ldl_solve_inplace(A, G);
+      linear_update(G, w);
+      out.ok = true;
+      return out;
+    }
+    {
+      // column 0 of H is the constraint sums, G + m up to rounding
+      double c[kM];
+#pragma unroll
+      for (int a = 0; a < kM; ++a) c[a] = G[a] + target(a);
+      hessian_direct(w, c, A);
+    }
     if (!ldl_factor_inplace(A)) return out;
     ldl_solve_inplace(A, G);  // G now holds the step
     if (r <= tol) {
@@ -560,7 +681,9 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
 #pragma unroll
       for (int a = 0; a < kM; ++a) G[a] *= sc;
     }
-    exp_update(G, w, max_step_exponent(G, 0.0) < 0.03);
+    const double big = max_step_exponent(G, 0.0);
+    exp_update(G, w, big);
+    reuse = LBM_NEWTON_REUSE_FACTORS && big < 1e-3;
   }
   return out;
 }

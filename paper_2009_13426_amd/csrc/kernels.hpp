@@ -234,7 +234,7 @@ __device__ __forceinline__ void node_uT(const S* f, const S* g, const int* tags,
 // source node s, rebuilt by Grad's ansatz from the moments and central
 // gradients at s (eq. GradGeneral with h* = h_eq + (1 - 1/tau) h_neq).
 template <typename S>
-__device__ __forceinline__ unsigned rebuild_link(const StepArgs a, int s, int Lx, int Ly, int k,
+__device__ __forceinline__ unsigned rebuild_link(const StepArgs& a, int s, int Lx, int Ly, int k,
                                               double& rf, double& rg, int& iters) {
   const S* f = static_cast<const S*>(a.fin);
   const S* g = static_cast<const S*>(a.gin);
@@ -531,7 +531,10 @@ void step_kernel(StepArgs a) {
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
           const double feq = rho * weight_of<k>(w);
-          eps += fabs(static_cast<double>(sh_pop[k][tid]) - feq) * rcp64(feq);
+          // one Newton-Raphson step on the hardware reciprocal: ~1e-14 relative
+          const double r0 = __builtin_amdgcn_rcp(feq);
+          const double ifeq = __builtin_fma(__builtin_fma(-feq, r0, 1.0), r0, r0);
+          eps += fabs(static_cast<double>(sh_pop[k][tid]) - feq) * ifeq;
         });
         tau *= sensor_alpha(eps * (1.0 / kQ));
       }
