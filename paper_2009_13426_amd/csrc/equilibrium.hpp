@@ -333,8 +333,14 @@ struct NewtonOut {
 };
 
 // Lattice-Maxwellian start (lambda_1 = -u/T, lambda_2 = I/(2T), the rest 0;
-// lambda_0 from the normalisation), FP64 exps throughout.  lam returns the
-// multipliers of the converged weights (before the final first-order step).
+// lambda_0 from the normalisation), weights always recomputed from the
+// multipliers.  Newton steps on the convex dual
+// Psi(lambda) = sum_i w_i(lambda) + lambda . m (gradient -G, Hessian H),
+// globalised by backtracking until Psi decreases by at least 1e-4 of the
+// linear prediction (a full step is also taken when it halves max |G|, since
+// near the root the change of Psi drops below its rounding).  lam returns
+// the multipliers of the converged weights (before the final first-order
+// step).
 __device__ __forceinline__ NewtonOut solve_robust(double ux, double uy, double T, double tol,
                                                   int max_iter, Weights& w, double (&l)[kM]) {
   NewtonOut out{0, false};
@@ -354,6 +360,7 @@ __device__ __forceinline__ NewtonOut solve_robust(double ux, double uy, double T
     double Z = w.w0;
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) Z += w.wp[p] + w.wm[p];
+    if (!(Z < 1e300) || !(Z > 1e-300)) return out;
     const double iZ = 1.0 / Z;
     w.w0 *= iZ;
 #pragma unroll
@@ -363,13 +370,22 @@ __device__ __forceinline__ NewtonOut solve_robust(double ux, double uy, double T
     }
     l[0] = log(Z) - 1.0;
   }
+  auto dual = [&](const Weights& v, const double (&lv)[kM]) {
+    double psi = v.w0;
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) psi += v.wp[p] + v.wm[p];
+#pragma unroll
+    for (int a = 0; a < kM; ++a) psi = __builtin_fma(lv[a], m[a], psi);
+    return psi;
+  };
+  double psi = dual(w, l);
   for (int it = 0; it < max_iter; ++it) {
     double S[kPairs], D[kPairs], G[kM], A[kTri], id[kM], d[kM];
     LowMoments LM;
     pair_sums(w, S, D);
     const double r = residual(S, D, w.w0, m, LM, G);
     out.iters = it + 1;
-    if (!(r < 1e300)) return out;
+    if (!(r < 1e300) || !(psi < 1e300)) return out;
     hessian(S, D, w.w0, LM, A);
     if (!ldl_factor(A, id)) return out;
     ldl_solve(A, id, G, d);
@@ -378,13 +394,34 @@ __device__ __forceinline__ NewtonOut solve_robust(double ux, double uy, double T
       out.ok = true;
       return out;
     }
-    double dmax = 0.0;
+    double slope = 0.0;  // directional derivative of Psi along d: -G . d < 0
 #pragma unroll
-    for (int a = 0; a < kM; ++a) dmax = fmax(dmax, fabs(d[a]));
-    const double sc = dmax > 1.0 ? 1.0 / dmax : 1.0;
+    for (int a = 0; a < kM; ++a) slope = __builtin_fma(-G[a], d[a], slope);
+    double t = 1.0;
+    for (;;) {
+      double lt[kM];
 #pragma unroll
-    for (int a = 0; a < kM; ++a) l[a] = __builtin_fma(sc, d[a], l[a]);
-    eval_weights(l, w);
+      for (int a = 0; a < kM; ++a) lt[a] = __builtin_fma(t, d[a], l[a]);
+      Weights wt;
+      eval_weights(lt, wt);
+      const double pt = dual(wt, lt);
+      bool take = pt < 1e300 && pt <= psi + 1e-4 * t * slope;
+      if (!take && t == 1.0 && pt < 1e300) {
+        double St[kPairs], Dt[kPairs], Gt[kM];
+        LowMoments Lt;
+        pair_sums(wt, St, Dt);
+        take = residual(St, Dt, wt.w0, m, Lt, Gt) < 0.5 * r;
+      }
+      if (take) {
+#pragma unroll
+        for (int a = 0; a < kM; ++a) l[a] = lt[a];
+        w = wt;
+        psi = pt;
+        break;
+      }
+      t *= 0.5;
+      if (t < 1e-12) return out;
+    }
   }
   return out;
 }
@@ -684,6 +721,21 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
     const double big = max_step_exponent(G, 0.0);
     exp_update(G, w, big);
     reuse = LBM_NEWTON_REUSE_FACTORS && big < 1e-3;
+  }
+  return out;
+}
+
+// solve_fast, and where it fails (a state far from the table or a start
+// from which plain Newton steps do not converge) the globalised solve_robust.
+__device__ __forceinline__ NewtonOut solve_equilibrium(const GuessTable& tb, double ux, double uy,
+                                                       double T, double tol, int max_iter,
+                                                       Weights& w) {
+  NewtonOut out = solve_fast(tb, ux, uy, T, tol, max_iter, w);
+  if (!out.ok) {
+    double l[kM];
+    const NewtonOut r = solve_robust(ux, uy, T, tol, max_iter, w, l);
+    out.iters += r.iters;
+    out.ok = r.ok;
   }
   return out;
 }

@@ -55,17 +55,38 @@ struct Grid {
   int fast_x, fast_y;  // wrap by one conditional add/sub (grid wider than any reach)
 };
 
+// Per-node side arrays carried from one step to the next.
+struct Carry {
+  unsigned* mask;      // links of the node's next pull whose source collided in another lattice
+  void* mac;           // [4][N] of S: rho, u'x, u'y, T of the last collision (lattice frame)
+  int* list;           // nodes with a non-zero mask (first *count entries)
+  unsigned* counters;  // [2]: list lengths, alternating with the step parity
+};
+
 struct StepArgs {
   const void* fin;
   const void* gin;
-  void* fout;
+  void* fout;  // on entry: the rebuilt links, each in its receiver's own slot
   void* gout;
   const int* tin;
   int* tout;
+  Carry carry;
   Grid grid;
   Phys phys;
   GuessTable table;
   int step;
+  DevDiag* diag;
+};
+
+struct RebuildArgs {
+  void* fout;       // buffer the coming step writes; rebuilt links go to their receiver's slot
+  void* gout;
+  const int* tags;  // current tags: Uc of every node, Un = lattice of its next pull
+  Carry carry;
+  Grid grid;
+  Phys phys;
+  GuessTable table;
+  int step;  // index of the coming step
   DevDiag* diag;
 };
 
@@ -218,58 +239,63 @@ __device__ __forceinline__ void grad_phi(const GradState& s, double cx, double c
   phig = kGradGCoeff * qc / (s.rho * P.Cp);
 }
 
-// Absolute macroscopic velocity and temperature of node s.
+// Storage type of the carried moments for population storage type S: S
+// itself (default), or FP64 in both forms with LBM_CARRY_FP64.
+#ifndef LBM_CARRY_FP64
+#define LBM_CARRY_FP64 0
+#endif
 template <typename S>
-__device__ __forceinline__ void node_uT(const S* f, const S* g, const int* tags, long long N,
-                                        long long s, double Cv, double& ux, double& uy,
-                                        double& T) {
-  double rho, upx, upy;
-  node_moments<S>(f, g, N, s, rho, upx, upy, T, Cv);
+using CarryT = typename std::conditional<LBM_CARRY_FP64 != 0, double, S>::type;
+
+// Absolute velocity and temperature of node s from the carried moments.
+template <typename S>
+__device__ __forceinline__ void carried_uT(const S* mac, const int* tags, long long N, long long s,
+                                           double& ux, double& uy, double& T) {
   const int t = tags[s];
-  ux = upx + tag_ucx(t);
-  uy = upy + tag_ucy(t);
+  ux = static_cast<double>(mac[N + s]) + tag_ucx(t);
+  uy = static_cast<double>(mac[2 * N + s]) + tag_ucy(t);
+  T = static_cast<double>(mac[3 * N + s]);
 }
 
-// Post-collision population of velocity plane k in lattice (Lx, Ly) at
-// source node s, rebuilt by Grad's ansatz from the moments and central
-// gradients at s (eq. GradGeneral with h* = h_eq + (1 - 1/tau) h_neq).
+// Post-collision population of velocity plane k in the receiver's lattice
+// (Lx, Ly), rebuilt at source node s by Grad's ansatz from the moments of
+// s's last collision and central differences of its neighbours' (eq.
+// GradGeneral with h* = h_eq + (1 - 1/tau) h_neq, tau = 1/2 + nu / T(s)).
 template <typename S>
-__device__ __forceinline__ unsigned rebuild_link(const StepArgs& a, int s, int Lx, int Ly, int k,
-                                              double& rf, double& rg, int& iters) {
-  const S* f = static_cast<const S*>(a.fin);
-  const S* g = static_cast<const S*>(a.gin);
+__device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long s, int Lx, int Ly,
+                                              int k, double& rf, double& rg, int& iters) {
+  const CarryT<S>* mac = static_cast<const CarryT<S>*>(a.carry.mac);
   const long long N = a.grid.N;
   const int nx = a.grid.nx, ny = a.grid.ny;
   const Phys& P = a.phys;
-  double rho, upx, upy, T;
-  node_moments<S>(f, g, N, s, rho, upx, upy, T, P.Cv);
-  const int ts = a.tin[s];
-  const double ux = upx + tag_ucx(ts), uy = upy + tag_ucy(ts);
+  const double rho = static_cast<double>(mac[s]);
+  double ux, uy, T;
+  carried_uT<CarryT<S>>(mac, a.tags, N, s, ux, uy, T);
   rf = 0.0;
   rg = 0.0;
   iters = 0;
   if (!(rho > 0.0) || !(T > 0.0) || !(rho < 1e300) || !(T < 1e300)) return kCodeNonphysical;
   double du[4] = {0.0, 0.0, 0.0, 0.0}, dT[2] = {0.0, 0.0};
   if (P.nu > 0.0) {
-    const int ys = s / nx, xs = s - ys * nx;
+    const int ys = static_cast<int>(s / nx), xs = static_cast<int>(s - static_cast<long long>(ys) * nx);
     const long long xp = (long long)ys * nx + wrapc(xs + 1, nx, a.grid.fast_x);
     const long long xm = (long long)ys * nx + wrapc(xs - 1, nx, a.grid.fast_x);
     const long long yp = (long long)wrapc(ys + 1, ny, a.grid.fast_y) * nx + xs;
     const long long ym = (long long)wrapc(ys - 1, ny, a.grid.fast_y) * nx + xs;
-    double uxp, uyp, Tp, uxm, uym, Tm;
-    node_uT<S>(f, g, a.tin, N, xp, P.Cv, uxp, uyp, Tp);
-    node_uT<S>(f, g, a.tin, N, xm, P.Cv, uxm, uym, Tm);
+    double uxp, uyp, Tp, uxm, uym, Tm, vxp, vyp, Sp, vxm, vym, Sm;
+    carried_uT<CarryT<S>>(mac, a.tags, N, xp, uxp, uyp, Tp);
+    carried_uT<CarryT<S>>(mac, a.tags, N, xm, uxm, uym, Tm);
+    carried_uT<CarryT<S>>(mac, a.tags, N, yp, vxp, vyp, Sp);
+    carried_uT<CarryT<S>>(mac, a.tags, N, ym, vxm, vym, Sm);
     du[0] = 0.5 * (uxp - uxm);
     du[2] = 0.5 * (uyp - uym);
     dT[0] = 0.5 * (Tp - Tm);
-    node_uT<S>(f, g, a.tin, N, yp, P.Cv, uxp, uyp, Tp);
-    node_uT<S>(f, g, a.tin, N, ym, P.Cv, uxm, uym, Tm);
-    du[1] = 0.5 * (uxp - uxm);
-    du[3] = 0.5 * (uyp - uym);
-    dT[1] = 0.5 * (Tp - Tm);
+    du[1] = 0.5 * (vxp - vxm);
+    du[3] = 0.5 * (vyp - vym);
+    dT[1] = 0.5 * (Sp - Sm);
   }
   Weights w;
-  const NewtonOut no = solve_fast(a.table, ux - Lx, uy - Ly, T, P.tol, P.max_iter, w);
+  const NewtonOut no = solve_equilibrium(a.table, ux - Lx, uy - Ly, T, P.tol, P.max_iter, w);
   iters = no.iters;
   if (!no.ok) return kCodeNewton;
   double wk = 0.0, cxk = 0.0, cyk = 0.0;
@@ -300,189 +326,109 @@ __device__ __forceinline__ double sensor_alpha(double eps) {
   return eps < 1e-2 ? 1.0 : (eps < 1e-1 ? 1.05 : (eps < 1.0 ? 1.35 : 2.0));
 }
 
+// Wrapped source columns and row offsets of node (x, y) for a pull in
+// lattice (ux, uy): link k's source is (x - cx - ux, y - cy - uy) and the
+// offsets cx + ux, cy + uy take seven values each (cx, cy in [-3, 3]).
+struct PullMap {
+  int col[7], row[7];
+  __device__ __forceinline__ void build(int x, int y, int ux, int uy, const Grid& g) {
+    static_for<0, 7>([&](auto ic) {
+      constexpr int c = decltype(ic)::value - 3;
+      col[c + 3] = wrapc(x - (c + ux), g.nx, g.fast_x);
+      row[c + 3] = wrapc(y - (c + uy), g.ny, g.fast_y) * g.nx;
+    });
+  }
+  template <int k>
+  __device__ __forceinline__ unsigned source() const {
+    return static_cast<unsigned>(row[plane_cy(k) + 3] + col[plane_cx(k) + 3]);
+  }
+};
+
 // ------------------------------------------------------------ fused step
 // One node per lane; BLOCK lanes per workgroup.  The pulled populations are
 // parked in LDS (plane-major, conflict-free) while the Newton solve holds
-// the registers, then read back for the collision.
+// the registers, then read back for the collision.  Links whose source
+// collided in another lattice were rebuilt beforehand (rebuild_kernel) into
+// the node's own slot of the output buffer and are read from there.  The
+// tail prepares the next step: moments of this collision, the mask of the
+// next pull's rebuilt links, and the list of nodes that have any.
 template <typename S, bool STREAM, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void step_kernel(StepArgs a) {
-  constexpr int WAVES = BLOCK / 64;
   __shared__ S sh_pop[2 * kQ][BLOCK];
-  __shared__ int sh_cnt[WAVES];
-  __shared__ int sh_src[BLOCK];
-  __shared__ int sh_meta[BLOCK];
-  __shared__ double sh_rf[BLOCK];
-  __shared__ double sh_rg[BLOCK];
-  __shared__ unsigned long long sh_stat[3 + LBM_HIST_BINS];
+  __shared__ unsigned long long sh_stat[2 + LBM_HIST_BINS];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const long long N = a.grid.N;
-  const int nx = a.grid.nx, ny = a.grid.ny;
+  const int nx = a.grid.nx;
   const long long n = static_cast<long long>(b) * BLOCK + tid;
   const bool active = n < N;
   const Phys& P = a.phys;
   const S* fin = static_cast<const S*>(a.fin);
   const S* gin = static_cast<const S*>(a.gin);
+  S* fout = static_cast<S*>(a.fout);
+  S* gout = static_cast<S*>(a.gout);
 
   if (P.stats) {
-    for (int i = tid; i < 3 + LBM_HIST_BINS; i += BLOCK) sh_stat[i] = 0ull;
+    for (int i = tid; i < 2 + LBM_HIST_BINS; i += BLOCK) sh_stat[i] = 0ull;
     __syncthreads();
   }
 
   int x = 0, y = 0, tag = 0;
+  unsigned mism = 0u;
   if (active) {
     y = static_cast<int>(n / nx);
     x = static_cast<int>(n - static_cast<long long>(y) * nx);
     tag = a.tin[n];
+    if constexpr (STREAM) mism = a.carry.mask[n];
   }
   // Shifts used for addressing are clamped to the admissible range, so no
   // tag content can move a pull outside the grid.
   const int unx = min(max(tag_unx(tag), -P.max_abs_shift), P.max_abs_shift);
   const int uny = min(max(tag_uny(tag), -P.max_abs_shift), P.max_abs_shift);
-  const int un16 = tag_un16(tag);
 
-  // Source node of link k is (x - cx - Ux, y - cy - Uy): with cx, cy in
-  // [-3, 3] the wrapped columns and row offsets take seven values each.
-  int col[7], row[7];
-  if constexpr (STREAM) {
-    static_for<0, 7>([&](auto ic) {
-      constexpr int c = decltype(ic)::value - 3;
-      col[c + 3] = wrapc(x - (c + unx), nx, a.grid.fast_x);
-      row[c + 3] = wrapc(y - (c + uny), ny, a.grid.fast_y) * nx;
-    });
-  }
-  auto source = [&](auto kc) -> unsigned {
-    constexpr int k = decltype(kc)::value;
-    if constexpr (STREAM)
-      return static_cast<unsigned>(row[plane_cy(k) + 3] + col[plane_cx(k) + 3]);
-    else
-      return static_cast<unsigned>(n);
-  };
-
-  // a1 (first half): which links have their source in another lattice
-  unsigned mism = 0u;
-  if constexpr (STREAM) {
-    if (active) {
-      int st[kQ];
-      static_for<0, kQ>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        st[k] = plane_at(a.tin, source(kc));
-      });
-      static_for<0, kQ>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        if (tag_uc16(st[k]) != un16) mism |= 1u << k;
-      });
-    }
-
-    // a2: those links are rebuilt by Grad's ansatz.  The block's
-    // (lane, link) items are packed and handed out one per lane, so a block
-    // pays ceil(items / BLOCK) rebuild rounds instead of one per distinct
-    // link; results go straight to the owner's LDS slots.
-    const int cnt = __popc(mism);
-    int v = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int t = __shfl_up(v, d, 64);
-      if (lane >= d) v += t;
-    }
-    if (lane == 63) sh_cnt[wave] = v;
-    __syncthreads();
-    int total = 0, wbase = 0;
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-      const int c = sh_cnt[w];
-      wbase += (w < wave) ? c : 0;
-      total += c;
-    }
-    const int off = wbase + v - cnt;
-    for (int r0 = 0; r0 < total; r0 += BLOCK) {
-      const bool mine = cnt > 0 && off < r0 + BLOCK && off + cnt > r0;
-      if (mine) {
-        int j = off;
-        static_for<0, kQ>([&](auto kc) {
-          constexpr int k = decltype(kc)::value;
-          if (mism & (1u << k)) {
-            if (j >= r0 && j < r0 + BLOCK) {
-              sh_src[j - r0] = static_cast<int>(source(kc));
-              sh_meta[j - r0] = k | ((unx & 0xFF) << 8) | ((uny & 0xFF) << 16);
-            }
-            ++j;
-          }
-        });
-      }
-      __syncthreads();
-      if (r0 + tid < total) {
-        const int meta = sh_meta[tid];
-        double rf, rg;
-        int it;
-        const unsigned code =
-            rebuild_link<S>(a, sh_src[tid], static_cast<int8_t>((meta >> 8) & 0xFF),
-                            static_cast<int8_t>((meta >> 16) & 0xFF), meta & 0xFF, rf, rg, it);
-        if (code) record_failure(a.diag, a.step, sh_src[tid], code);
-        sh_rf[tid] = rf;
-        sh_rg[tid] = rg;
-        if (P.stats) {
-          atomicAdd(&sh_stat[0], 1ull);
-          atomicAdd(&sh_stat[1], static_cast<unsigned long long>(it));
-          atomicAdd(&sh_stat[3 + (it < LBM_HIST_BINS ? it : LBM_HIST_BINS - 1)], 1ull);
-        }
-      }
-      __syncthreads();
-      if (mine) {
-        int j = off;
-        static_for<0, kQ>([&](auto kc) {
-          constexpr int k = decltype(kc)::value;
-          if (mism & (1u << k)) {
-            if (j >= r0 && j < r0 + BLOCK) {
-              sh_pop[k][tid] = static_cast<S>(sh_rf[j - r0]);
-              sh_pop[kQ + k][tid] = static_cast<S>(sh_rg[j - r0]);
-            }
-            ++j;
-          }
-        });
-      }
-      __syncthreads();
-    }
-    if (P.stats && cnt) atomicAdd(&sh_stat[2], static_cast<unsigned long long>(cnt));
-  }
-
-  // a1 (second half) and a3: every link is loaded (all loads in flight at
-  // once), rebuilt links then replace theirs from LDS by a select; the
-  // merged populations are parked in LDS and their moments taken in the
-  // frame of the node's lattice (eq. polyTemp)
+  // a1 and a3: every link loaded (all loads in flight at once) from its
+  // source, or from this node's slot of the output buffer where rebuilt;
+  // parked in LDS; moments in the frame of the node's lattice (eq. polyTemp)
   double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
   if (active) {
     S fv[kQ], gv[kQ];
-    static_for<0, kQ>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      const unsigned s = source(kc);
-      fv[k] = plane_at(fin + k * N, s);
-      gv[k] = plane_at(gin + k * N, s);
-    });
+    if constexpr (STREAM) {
+      PullMap pm;
+      pm.build(x, y, unx, uny, a.grid);
+      static_for<0, kQ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const bool m = (mism >> k) & 1u;
+        const S* pf = m ? static_cast<const S*>(fout) + k * N : fin + k * N;
+        const S* pg = m ? static_cast<const S*>(gout) + k * N : gin + k * N;
+        const unsigned i = m ? static_cast<unsigned>(n) : pm.template source<k>();
+        fv[k] = plane_at(pf, i);
+        gv[k] = plane_at(pg, i);
+      });
+    } else {
+      static_for<0, kQ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        fv[k] = plane_at(fin + k * N, static_cast<unsigned>(n));
+        gv[k] = plane_at(gin + k * N, static_cast<unsigned>(n));
+      });
+    }
     static_for<0, kQ>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
       constexpr int cx = plane_cx(k), cy = plane_cy(k);
-      S fk = fv[k], gk = gv[k];
-      if constexpr (STREAM) {
-        const bool m = (mism >> k) & 1u;
-        const S rf = sh_pop[k][tid], rg = sh_pop[kQ + k][tid];
-        fk = m ? rf : fk;
-        gk = m ? rg : gk;
-      }
-      sh_pop[k][tid] = fk;
-      sh_pop[kQ + k][tid] = gk;
-      const double fd = static_cast<double>(fk);
+      sh_pop[k][tid] = fv[k];
+      sh_pop[kQ + k][tid] = gv[k];
+      const double fd = static_cast<double>(fv[k]);
       rho += fd;
       jx = cmad<cx>(jx, fd);
       jy = cmad<cy>(jy, fd);
-      e = cmad<cx * cx + cy * cy>(e, fd) + static_cast<double>(gk);
+      e = cmad<cx * cx + cy * cy>(e, fd) + static_cast<double>(gv[k]);
     });
   }
   // the populations now live in LDS only; the solve gets the registers
   asm volatile("" ::: "memory");
 
+  unsigned next_mask = 0u;
   if (active) {
     const double upx = jx / rho, upy = jy / rho;
     const double T = (e - rho * (upx * upx + upy * upy)) / (2.0 * rho * P.Cv);
@@ -490,32 +436,47 @@ void step_kernel(StepArgs a) {
     int nux = unx, nuy = uny;
     Weights w;
     int iters = 0;
-    if (!(rho > 0.0) || !(T > 0.0) || !(rho < 1e300) || !(T < 1e300) || !(fabs(upx) < 1e300) ||
-        !(fabs(upy) < 1e300)) {
+    const bool physical = rho > 0.0 && T > 0.0 && rho < 1e300 && T < 1e300 &&
+                          fabs(upx) < 1e300 && fabs(upy) < 1e300;
+    if (!physical) {
       code = kCodeNonphysical;
-    } else {
+    } else if (P.shift_mode == 0) {
       // a4: lattice of the next pull
-      if (P.shift_mode == 0) {
-        nux = select_axis(upx + unx, unx, P.halfwidth);
-        nuy = select_axis(upy + uny, uny, P.halfwidth);
-        if (abs(nux) > P.max_abs_shift || abs(nuy) > P.max_abs_shift) {
-          code = kCodeNonphysical;
-          nux = unx;  // keep every stored shift in range: later pulls stay in bounds
-          nuy = uny;
-        }
+      nux = select_axis(upx + unx, unx, P.halfwidth);
+      nuy = select_axis(upy + uny, uny, P.halfwidth);
+      if (abs(nux) > P.max_abs_shift || abs(nuy) > P.max_abs_shift) {
+        code = kCodeNonphysical;
+        nux = unx;  // keep every stored shift in range: later pulls stay in bounds
+        nuy = uny;
       }
+    }
+    // links of the next pull whose source collides in another lattice this
+    // step (the source's lattice of this step is the Un half of its tag)
+    if (P.shift_mode != 1) {
+      PullMap pm;
+      pm.build(x, y, nux, nuy, a.grid);
+      const int nun16 = (nux & 0xFF) | ((nuy & 0xFF) << 8);
+      int st[kQ];
+      static_for<0, kQ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        st[k] = plane_at(a.tin, pm.template source<k>());
+      });
+      static_for<0, kQ>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        if (tag_un16(st[k]) != nun16) next_mask |= 1u << k;
+      });
+    }
+    if (physical) {
       // a5: numerical equilibrium
-      const NewtonOut no = solve_fast(a.table, upx, upy, T, P.tol, P.max_iter, w);
+      const NewtonOut no = solve_equilibrium(a.table, upx, upy, T, P.tol, P.max_iter, w);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
     if (P.stats) {
       atomicAdd(&sh_stat[0], 1ull);
       atomicAdd(&sh_stat[1], static_cast<unsigned long long>(iters));
-      atomicAdd(&sh_stat[3 + (iters < LBM_HIST_BINS ? iters : LBM_HIST_BINS - 1)], 1ull);
+      atomicAdd(&sh_stat[2 + (iters < LBM_HIST_BINS ? iters : LBM_HIST_BINS - 1)], 1ull);
     }
-    S* fout = static_cast<S*>(a.fout);
-    S* gout = static_cast<S*>(a.gout);
     if (code) {
       record_failure(a.diag, a.step, n, code);
       static_for<0, kQ>([&](auto kc) {
@@ -550,22 +511,138 @@ void step_kernel(StepArgs a) {
           plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, geq - gk, gk);
         } else {
           const float omf = static_cast<float>(om);
-          plane_at(fout + k * N, static_cast<unsigned>(n)) = __builtin_fmaf(omf, static_cast<float>(feq) - fk, fk);
-          plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fmaf(omf, static_cast<float>(geq) - gk, gk);
+          plane_at(fout + k * N, static_cast<unsigned>(n)) =
+              __builtin_fmaf(omf, static_cast<float>(feq) - fk, fk);
+          plane_at(gout + k * N, static_cast<unsigned>(n)) =
+              __builtin_fmaf(omf, static_cast<float>(geq) - gk, gk);
         }
       });
     }
     a.tout[n] = tag_pack(unx, uny, nux, nuy);
+    a.carry.mask[n] = next_mask;
+    CarryT<S>* mac = static_cast<CarryT<S>*>(a.carry.mac);
+    mac[n] = static_cast<CarryT<S>>(rho);
+    mac[N + n] = static_cast<CarryT<S>>(upx);
+    mac[2 * N + n] = static_cast<CarryT<S>>(upy);
+    mac[3 * N + n] = static_cast<CarryT<S>>(T);
+  }
+
+  // nodes with rebuilt links next step go to the list (one atomic per wave)
+  {
+    const unsigned long long bal = __ballot(next_mask != 0u);
+    if (bal) {
+      const int lane = tid & 63;
+      const int leader = __ffsll(static_cast<long long>(bal)) - 1;
+      unsigned base = 0;
+      if (lane == leader)
+        base = atomicAdd(&a.carry.counters[a.step & 1], static_cast<unsigned>(__popcll(bal)));
+      base = __shfl(base, leader, 64);
+      if (next_mask)
+        a.carry.list[base + __popcll(bal & ((1ull << lane) - 1ull))] = static_cast<int>(n);
+    }
   }
 
   if (P.stats) {
     __syncthreads();
-    if (tid < 3 + LBM_HIST_BINS && sh_stat[tid]) {
+    if (tid < 2 + LBM_HIST_BINS && sh_stat[tid]) {
       unsigned long long* dst = tid == 0   ? &a.diag->newton_calls
                                 : tid == 1 ? &a.diag->newton_iters
-                                : tid == 2 ? &a.diag->mismatched
-                                           : &a.diag->hist[tid - 3];
+                                           : &a.diag->hist[tid - 2];
       atomicAdd(dst, sh_stat[tid]);
+    }
+  }
+}
+
+// ------------------------------------------------------------ rebuild
+// a2: rebuilds, before a step, every link of that step's pull whose source
+// collided in another lattice, into the receiver's slot of the buffer the
+// step writes.  The list holds the receivers; each wave expands its 64
+// receivers' links into (receiver, link) items and hands them out one per
+// lane.  Grid-stride over the list; clears the other list counter for the
+// coming step's appends.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void rebuild_kernel(RebuildArgs a) {
+  __shared__ int sh_node[kWaves][64];
+  __shared__ int sh_k[kWaves][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned count = a.carry.counters[(a.step - 1) & 1];
+  if (blockIdx.x == 0 && tid == 0) a.carry.counters[a.step & 1] = 0u;
+  const Phys& P = a.phys;
+  const long long N = a.grid.N;
+  const int nx = a.grid.nx;
+  S* fout = static_cast<S*>(a.fout);
+  S* gout = static_cast<S*>(a.gout);
+  const long long waves = static_cast<long long>(gridDim.x) * kWaves;
+  for (long long base = (static_cast<long long>(blockIdx.x) * kWaves + wave) * 64; base < count;
+       base += waves * 64) {
+    const long long i = base + lane;
+    int node = 0;
+    unsigned msk = 0u;
+    if (i < count) {
+      node = a.carry.list[i];
+      msk = a.carry.mask[node];
+    }
+    // exclusive prefix of the link counts over the wave
+    const int cnt = __popc(msk);
+    int v = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int t = __shfl_up(v, d, 64);
+      if (lane >= d) v += t;
+    }
+    const int total = __shfl(v, 63, 64);
+    const int off = v - cnt;
+    for (int r0 = 0; r0 < total; r0 += 64) {
+      // scatter this round's items to their lanes
+      if (cnt > 0 && off < r0 + 64 && off + cnt > r0) {
+        int j = off;
+        unsigned m = msk;
+        while (m) {
+          const int k = __ffs(m) - 1;
+          m &= m - 1u;
+          if (j >= r0 && j < r0 + 64) {
+            sh_node[wave][j - r0] = node;
+            sh_k[wave][j - r0] = k;
+          }
+          ++j;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (r0 + lane < total) {
+        const int xn = sh_node[wave][lane];
+        const int k = sh_k[wave][lane];
+        const int t = a.tags[xn];
+        const int Lx = min(max(tag_unx(t), -P.max_abs_shift), P.max_abs_shift);
+        const int Ly = min(max(tag_uny(t), -P.max_abs_shift), P.max_abs_shift);
+        const int yx = xn / nx, xx = xn - yx * nx;
+        int cx = 0, cy = 0;
+        static_for<0, kQ>([&](auto kc) {
+          constexpr int kk = decltype(kc)::value;
+          if (k == kk) {
+            cx = plane_cx(kk);
+            cy = plane_cy(kk);
+          }
+        });
+        const long long s = static_cast<long long>(wrapc(yx - (cy + Ly), a.grid.ny, a.grid.fast_y)) * nx +
+                            wrapc(xx - (cx + Lx), nx, a.grid.fast_x);
+        double rf, rg;
+        int it;
+        const unsigned code = rebuild_link<S>(a, s, Lx, Ly, k, rf, rg, it);
+        if (code) record_failure(a.diag, a.step, s, code);
+        plane_at(fout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rf);
+        plane_at(gout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rg);
+        if (P.stats) {
+          atomicAdd(&a.diag->mismatched, 1ull);
+          atomicAdd(&a.diag->newton_calls, 1ull);
+          atomicAdd(&a.diag->newton_iters, static_cast<unsigned long long>(it));
+          atomicAdd(&a.diag->hist[it < LBM_HIST_BINS ? it : LBM_HIST_BINS - 1], 1ull);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
 }
@@ -640,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a) {
   a.tout[n] = tag_pack(Ux, Uy, Ux, Uy);
   Weights w;
   if (!code) {
-    const NewtonOut no = solve_fast(a.table, ux - Ux, uy - Uy, T, P.tol, P.max_iter, w);
+    const NewtonOut no = solve_equilibrium(a.table, ux - Ux, uy - Uy, T, P.tol, P.max_iter, w);
     if (!no.ok) code = kCodeNewton;
   }
   if (code) {

@@ -23,11 +23,12 @@ namespace {
 
 constexpr size_t kAlign = 256;
 
-// Initial-guess table: |u'| in [0, 1] (step 1/32), 1/T in [0.5, 1/0.3]
-// (35 levels), 8 floats per point.
-constexpr int kTabU = 33;
+// Initial-guess table: |u'_x|, |u'_y| in [0, 2] (step 1/32), 1/T in
+// [0.5, 1/0.3] (35 levels), 8 floats per point (4.7 MB; the states of a flow
+// touch a small part of it).
+constexpr int kTabU = 65;
 constexpr int kTabS = 35;
-constexpr float kTabUmax = 1.0f;
+constexpr float kTabUmax = 2.0f;
 constexpr float kTabSmin = 0.5f;
 constexpr float kTabSmax = 1.0f / 0.3f;
 
@@ -38,6 +39,7 @@ struct Layout {
   size_t tag_bytes;
   size_t diag_off, part_off, sums_off, table_off, total;
   size_t off_pop[2], off_tag[2];
+  size_t mac_off, mask_off, list_off, count_off;  // carried from step to step
   int nparts;
 };
 
@@ -70,6 +72,14 @@ Layout layout(const lbm_config* c) {
     L.off_tag[b] = off;
     off += L.tag_bytes;
   }
+  L.mac_off = off;
+  off += align_up(4 * N * (LBM_CARRY_FP64 ? sizeof(double) : es));
+  L.mask_off = off;
+  off += align_up(N * sizeof(unsigned));
+  L.list_off = off;
+  off += align_up(N * sizeof(int));
+  L.count_off = off;
+  off += align_up(2 * sizeof(unsigned));
   L.diag_off = off;
   off += align_up(sizeof(DevDiag));
   L.part_off = off;
@@ -98,6 +108,7 @@ struct lbm_ctx {
   GuessTable table;
   int nblocks;       // 256-lane blocks (init, exports, reductions)
   int step_blocks;   // blocks of the step kernel
+  int rebuild_blocks;  // blocks of the (grid-stride) rebuild kernel
 
   void* f(int b) const { return ws + lay.off_pop[b]; }
   void* g(int b) const {
@@ -105,6 +116,14 @@ struct lbm_ctx {
     return ws + lay.off_pop[b] + kQ * static_cast<size_t>(grid.N) * es;
   }
   int* tag(int b) const { return reinterpret_cast<int*>(ws + lay.off_tag[b]); }
+  Carry carry() const {
+    Carry k;
+    k.mask = reinterpret_cast<unsigned*>(ws + lay.mask_off);
+    k.mac = ws + lay.mac_off;
+    k.list = reinterpret_cast<int*>(ws + lay.list_off);
+    k.counters = reinterpret_cast<unsigned*>(ws + lay.count_off);
+    return k;
+  }
   DevDiag* diag() const { return reinterpret_cast<DevDiag*>(ws + lay.diag_off); }
   double* parts() const { return reinterpret_cast<double*>(ws + lay.part_off); }
   double* sums() const { return reinterpret_cast<double*>(ws + lay.sums_off); }
@@ -117,12 +136,14 @@ struct lbm_ctx {
 
 namespace {
 
-// Device-side clean diagnostics record (fail_key = ~0, counters 0).
-__global__ void diag_reset_kernel(DevDiag* d) {
+// Device-side clean diagnostics record (fail_key = ~0, counters 0) and
+// empty rebuild lists.
+__global__ void diag_reset_kernel(DevDiag* d, unsigned* list_counters) {
   const int i = threadIdx.x;
   unsigned long long* w = reinterpret_cast<unsigned long long*>(d);
   const int n = static_cast<int>(sizeof(DevDiag) / sizeof(unsigned long long));
   if (i < n) w[i] = (i == 0) ? ~0ull : 0ull;
+  if (i < 2) list_counters[i] = 0u;
 }
 
 lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step) {
@@ -133,6 +154,7 @@ lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step)
   a.gout = c->g(dst);
   a.tin = c->tag(src);
   a.tout = c->tag(dst);
+  a.carry = c->carry();
   a.grid = c->grid;
   a.phys = c->phys;
   a.table = c->table;
@@ -155,6 +177,28 @@ lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step)
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
 }
 
+// Rebuilds the mismatched links of step `step` (pulling from buffer src)
+// into buffer dst.  Nothing to do with one lattice for all nodes.
+lbm_status launch_rebuild(lbm_ctx* c, int src, int dst, int step) {
+  if (c->cfg.shift_mode == LBM_SHIFT_FIXED) return LBM_OK;
+  RebuildArgs a;
+  a.fout = c->f(dst);
+  a.gout = c->g(dst);
+  a.tags = c->tag(src);
+  a.carry = c->carry();
+  a.grid = c->grid;
+  a.phys = c->phys;
+  a.table = c->table;
+  a.step = step;
+  a.diag = c->diag();
+  const dim3 grid(c->rebuild_blocks);
+  if (c->cfg.precision == LBM_FP64)
+    hipLaunchKernelGGL(rebuild_kernel<double>, grid, dim3(kBlock), 0, c->stream, a);
+  else
+    hipLaunchKernelGGL(rebuild_kernel<float>, grid, dim3(kBlock), 0, c->stream, a);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
 lbm_status read_status(lbm_ctx* c, unsigned long long* key_out) {
   unsigned long long key = ~0ull;
   HIP_TRY(hipMemcpyAsync(&key, &c->diag()->fail_key, sizeof key, hipMemcpyDeviceToHost,
@@ -169,7 +213,8 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
                        const double* T, const int8_t* sux, const int8_t* suy) {
   if (!c || !rho || !ux || !uy || !T) return LBM_ERR_ARG;
   if (c->cfg.shift_mode == LBM_SHIFT_STATIC && (!sux || !suy)) return LBM_ERR_ARG;
-  hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag());
+  hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
+                     c->carry().counters);
   InitArgs a;
   a.rho = rho;
   a.ux = ux;
@@ -268,6 +313,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* strea
   {
     const int B = cfg->precision == LBM_FP64 ? step_block<double>() : step_block<float>();
     c->step_blocks = static_cast<int>((c->grid.N + B - 1) / B);
+    c->rebuild_blocks = static_cast<int>(std::min<long long>((c->grid.N + kBlock - 1) / kBlock, 2048));
   }
   c->table.data = reinterpret_cast<const float*>(c->ws + L.table_off);
   c->table.nu = kTabU;
@@ -277,7 +323,8 @@ lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* strea
   c->table.smax = kTabSmax;
   c->table.inv_hu = (kTabU - 1) / kTabUmax;
   c->table.inv_hs = (kTabS - 1) / (kTabSmax - kTabSmin);
-  hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag());
+  hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
+                     c->carry().counters);
   {
     const int pts = kTabU * kTabU * kTabS;
     hipLaunchKernelGGL(table_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream,
@@ -312,7 +359,10 @@ lbm_status lbm_step_async(lbm_ctx* c, int32_t nsteps) {
   if (!c->initialized) return LBM_ERR_STATE;
   for (int32_t k = 0; k < nsteps; ++k) {
     const int src = c->cur, dst = 1 - c->cur;
-    lbm_status st = launch_step(c, src, dst, true, static_cast<int>(c->steps_done + 1));
+    const int step = static_cast<int>(c->steps_done + 1);
+    lbm_status st = launch_rebuild(c, src, dst, step);
+    if (st) return st;
+    st = launch_step(c, src, dst, true, step);
     if (st) return st;
     c->cur = dst;
     c->steps_done += 1;
