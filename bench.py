@@ -33,29 +33,28 @@ Q = 21
 
 def bytes_per_node(precision):
     """Algorithmic HBM bytes per node update of the step kernel: read and
-    write 2 x 21 populations, read and write the node's own lattice tag."""
+    write 2 x 21 populations, read and write the node's lattice tag and its
+    rebuilt-link mask (4 bytes each), write the four moments of the
+    collision that the next step's link rebuild reads."""
     es = 8 if precision == "fp64" else 4
-    return 2 * 2 * Q * es + 2 * 4
+    return 2 * 2 * Q * es + 2 * 4 + 2 * 4 + 4 * es
 
 
 def time_form(lbm, torch, wl, precision, steps, warmup):
+    """Timed region: `steps` steps between two synchronisations, HIP events
+    around every launch on the library's stream (step and link-rebuild
+    kernels timed separately)."""
     sim = lbm.Sim.from_workload(wl, precision=precision)
     sim.step(warmup)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record(sim.stream)
-    sim.step_async(steps)
-    ev1.record(sim.stream)
-    sim.sync()
+    ms_rebuild, ms_step = sim.step_profiled(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = ev0.elapsed_time(ev1) / steps
     d = sim.diag()
     nodes = wl.nx * wl.ny
-    out = dict(ms_per_step=wall * 1e3 / steps, kernel_ms=kern_ms,
-               mlups=nodes * steps / wall / 1e6,
+    out = dict(ms_per_step=wall * 1e3 / steps, kernel_ms=ms_step / steps,
+               rebuild_ms=ms_rebuild / steps, mlups=nodes * steps / wall / 1e6,
                conserved=d["conserved"], status=d["status"])
     sim.close()
     return out
@@ -133,8 +132,9 @@ def main():
         print(f"[bench] timing {form} {args.size}^2, warmup {args.warmup}, steps {args.steps}",
               file=sys.stderr, flush=True)
         res[form] = time_form(lbm, torch, wl, form, args.steps, args.warmup)
-        print(f"[bench] {form}: {res[form]['mlups']:.1f} MLUPS, "
-              f"kernel {res[form]['kernel_ms']:.3f} ms/step", file=sys.stderr, flush=True)
+        print(f"[bench] {form}: {res[form]['mlups']:.1f} MLUPS, step kernel "
+              f"{res[form]['kernel_ms']:.3f} ms, rebuild kernel {res[form]['rebuild_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
     head = "fp32" if "fp32" in res else next(iter(res))
     print("[bench] counters pass", file=sys.stderr, flush=True)
     counters = {f: stats_pass(lbm, wl, f, 5) for f in res}
@@ -159,6 +159,7 @@ def main():
                     nodes=nodes, precision=head),
         roofline=roofline, cpu_baseline=cpu,
         forms={f: dict(mlups=round(r["mlups"], 2), kernel_ms=round(r["kernel_ms"], 4),
+                       rebuild_ms=round(r["rebuild_ms"], 4),
                        hbm_gbs=round(bytes_per_node(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9, 1),
                        bytes_per_node=bytes_per_node(f), **counters[f])
                for f, r in res.items()},

@@ -134,6 +134,12 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t nsteps);
  * or checking; lbm_sync (or any synchronous call) reports errors later. */
 lbm_status lbm_step_async(lbm_ctx* ctx, int32_t nsteps);
 
+/* As lbm_step for nsteps >= 1, with HIP events recorded on the context's
+ * stream around every launch.  ms_rebuild, ms_step (host pointers): summed
+ * durations in milliseconds of the link-rebuild launches (0 when the
+ * lattice is fixed) and of the step launches.  Synchronous; for measurement. */
+lbm_status lbm_step_profiled(lbm_ctx* ctx, int32_t nsteps, double* ms_rebuild, double* ms_step);
+
 /* Waits for the context's stream and returns the device error status. */
 lbm_status lbm_sync(lbm_ctx* ctx);
 

@@ -124,6 +124,14 @@ class Sim:
     def step_async(self, n: int = 1):
         _check(lib.lbm_step_async(self._ctx, int(n)), "lbm_step_async")
 
+    def step_profiled(self, n: int):
+        """n steps with HIP events around every launch; returns the summed
+        (rebuild, step) launch durations in milliseconds."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib.lbm_step_profiled(self._ctx, int(n), C.byref(a), C.byref(b)),
+               "lbm_step_profiled")
+        return a.value, b.value
+
     def sync(self):
         _check(lib.lbm_sync(self._ctx), "lbm_sync")
 

@@ -39,6 +39,8 @@ SIGNATURES = {
     "lbm_init_fields_static": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_step_async": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lbm_step_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
     "lbm_sync": (C.c_int, [C.c_void_p]),
     "lbm_get_macros": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "lbm_get_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -399,13 +399,20 @@ void step_kernel(StepArgs a) {
       pm.build(x, y, unx, uny, a.grid);
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const bool m = (mism >> k) & 1u;
-        const S* pf = m ? static_cast<const S*>(fout) + k * N : fin + k * N;
-        const S* pg = m ? static_cast<const S*>(gout) + k * N : gin + k * N;
-        const unsigned i = m ? static_cast<unsigned>(n) : pm.template source<k>();
-        fv[k] = plane_at(pf, i);
-        gv[k] = plane_at(pg, i);
+        const unsigned i = pm.template source<k>();
+        fv[k] = plane_at(fin + k * N, i);
+        gv[k] = plane_at(gin + k * N, i);
       });
+      // rebuilt links (rare: a wave-uniform test skips this for most waves)
+      if (__ballot(mism != 0u)) {
+        static_for<0, kQ>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          if ((mism >> k) & 1u) {
+            fv[k] = plane_at(static_cast<const S*>(fout) + k * N, static_cast<unsigned>(n));
+            gv[k] = plane_at(static_cast<const S*>(gout) + k * N, static_cast<unsigned>(n));
+          }
+        });
+      }
     } else {
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
@@ -572,13 +579,16 @@ __global__ __launch_bounds__(kBlock) void rebuild_kernel(RebuildArgs a) {
   const int nx = a.grid.nx;
   S* fout = static_cast<S*>(a.fout);
   S* gout = static_cast<S*>(a.gout);
+  // kChunk receivers per wave and pass: a receiver has up to 21 links, so
+  // small chunks spread the items over many waves
+  constexpr int kChunk = 16;
   const long long waves = static_cast<long long>(gridDim.x) * kWaves;
-  for (long long base = (static_cast<long long>(blockIdx.x) * kWaves + wave) * 64; base < count;
-       base += waves * 64) {
+  for (long long base = (static_cast<long long>(blockIdx.x) * kWaves + wave) * kChunk; base < count;
+       base += waves * kChunk) {
     const long long i = base + lane;
     int node = 0;
     unsigned msk = 0u;
-    if (i < count) {
+    if (lane < kChunk && i < count) {
       node = a.carry.list[i];
       msk = a.carry.mask[node];
     }

@@ -313,7 +313,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* strea
   {
     const int B = cfg->precision == LBM_FP64 ? step_block<double>() : step_block<float>();
     c->step_blocks = static_cast<int>((c->grid.N + B - 1) / B);
-    c->rebuild_blocks = static_cast<int>(std::min<long long>((c->grid.N + kBlock - 1) / kBlock, 2048));
+    c->rebuild_blocks = static_cast<int>(std::min<long long>((c->grid.N + kBlock - 1) / kBlock, 4096));
   }
   c->table.data = reinterpret_cast<const float*>(c->ws + L.table_off);
   c->table.nu = kTabU;
@@ -368,6 +368,46 @@ lbm_status lbm_step_async(lbm_ctx* c, int32_t nsteps) {
     c->steps_done += 1;
   }
   return LBM_OK;
+}
+
+lbm_status lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_rebuild, double* ms_step) {
+  if (!c || nsteps < 1 || !ms_rebuild || !ms_step) return LBM_ERR_ARG;
+  if (!c->initialized) return LBM_ERR_STATE;
+  *ms_rebuild = 0.0;
+  *ms_step = 0.0;
+  std::vector<hipEvent_t> ev(2 * static_cast<size_t>(nsteps) + 1, nullptr);
+  lbm_status st = LBM_OK;
+  for (auto& e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      st = LBM_ERR_HIP;
+    }
+  if (st == LBM_OK && hipEventRecord(ev[0], c->stream) != hipSuccess) st = LBM_ERR_HIP;
+  for (int32_t k = 0; k < nsteps && st == LBM_OK; ++k) {
+    const int src = c->cur, dst = 1 - c->cur;
+    const int step = static_cast<int>(c->steps_done + 1);
+    st = launch_rebuild(c, src, dst, step);
+    if (st == LBM_OK && hipEventRecord(ev[2 * k + 1], c->stream) != hipSuccess) st = LBM_ERR_HIP;
+    if (st == LBM_OK) st = launch_step(c, src, dst, true, step);
+    if (st == LBM_OK && hipEventRecord(ev[2 * k + 2], c->stream) != hipSuccess) st = LBM_ERR_HIP;
+    if (st == LBM_OK) {
+      c->cur = dst;
+      c->steps_done += 1;
+    }
+  }
+  if (st == LBM_OK && hipEventSynchronize(ev.back()) != hipSuccess) st = LBM_ERR_HIP;
+  for (int32_t k = 0; k < nsteps && st == LBM_OK; ++k) {
+    float a = 0.0f, b = 0.0f;
+    if (hipEventElapsedTime(&a, ev[2 * k], ev[2 * k + 1]) != hipSuccess ||
+        hipEventElapsedTime(&b, ev[2 * k + 1], ev[2 * k + 2]) != hipSuccess)
+      st = LBM_ERR_HIP;
+    *ms_rebuild += a;
+    *ms_step += b;
+  }
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (st) return st;
+  return read_status(c, nullptr);
 }
 
 lbm_status lbm_sync(lbm_ctx* c) {
