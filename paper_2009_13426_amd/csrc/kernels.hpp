@@ -657,11 +657,12 @@ __global__ __launch_bounds__(kBlock) void rebuild_kernel(RebuildArgs a) {
   }
 }
 
-// Population storage type -> lanes per workgroup of the step kernel (the
-// LDS parking area is 42 x BLOCK values: 43 KB either way).
+// Lanes per workgroup of the step kernel: one wave.  The LDS parking area is
+// 42 x 64 values per wave (10.5 KB FP32, 21 KB FP64); single-wave blocks let
+// the LDS-bound FP64 form fit 7 waves per CU instead of 6.
 template <typename S>
 constexpr int step_block() {
-  return std::is_same<S, double>::value ? 128 : 256;
+  return 64;
 }
 
 // Builds the initial-guess table: one lane per grid point, Maxwellian-start
