@@ -13,9 +13,18 @@ Newton); the FP64 form is timed the same way and reported beside it.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--size L] [--no-cpu]
 
 One JSON line on stdout.  Inputs are resident on the GPU before timing
-starts; the timed region is K steps between two synchronisations, and the
-step kernel's own average duration is measured with HIP events on the stream
-the library launches on.
+starts; the timed region is K steps between two synchronisations, with HIP
+events around every launch on the stream the library launches on (the step
+kernel and the link-rebuild kernel are timed separately).
+
+The step kernel is bound by FP64 vector arithmetic (the Newton solve), so
+`roofline` is the ALU one: FP64 flops per node update (counted by rocprofv3
+for this kernel on this workload, read from the committed summary in
+profiles/) times the nodes of one launch, over the kernel's event-timed
+duration, against the FP64 vector peak.  Its `traffic` is the HBM bytes one
+launch moves (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), reported
+only while the summary was taken on the current kernel sources; `hbm` gives
+the algorithmic-byte rate against the 8 TB/s peak.
 """
 import argparse
 import json
@@ -28,7 +37,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz)
+VALU_ISSUE_PEAK = 256 * 4 * 64 / 4 * 2.4e9   # wave64 VALU instructions: lanes per second
 Q = 21
+PROFILE = os.path.join(ROOT, "profiles", "step_kernel_four_quadrant_4096.txt")
 
 
 def bytes_per_node(precision):
@@ -38,6 +50,34 @@ def bytes_per_node(precision):
     collision that the next step's link rebuild reads."""
     es = 8 if precision == "fp64" else 4
     return 2 * 2 * Q * es + 2 * 4 + 2 * 4 + 4 * es
+
+
+def kernel_sources_digest():
+    """sha256 over the HIP sources (the counter figures in the profile are
+    valid only for the kernels they were taken on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2009_13426_amd", "csrc")
+    for path in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def profile_figures():
+    """Per-form counter figures of the step kernel from the committed
+    rocprofv3 summary: lines 'key: value', keys '<form>.<name>'."""
+    out = {}
+    try:
+        with open(PROFILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    out[k.strip()] = v.strip()
+    except OSError:
+        return {}
+    return out
 
 
 def time_form(lbm, torch, wl, precision, steps, warmup):
@@ -103,6 +143,8 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the extra run with Newton and rebuild counters")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times "
                          "(calibrates the HBM byte counters) and exit")
@@ -136,13 +178,32 @@ def main():
               f"{res[form]['kernel_ms']:.3f} ms, rebuild kernel {res[form]['rebuild_ms']:.3f} ms",
               file=sys.stderr, flush=True)
     head = "fp32" if "fp32" in res else next(iter(res))
-    print("[bench] counters pass", file=sys.stderr, flush=True)
-    counters = {f: stats_pass(lbm, wl, f, 5) for f in res}
+    counters = {f: {} for f in res}
+    if not args.no_counters:
+        print("[bench] counters pass", file=sys.stderr, flush=True)
+        counters = {f: stats_pass(lbm, wl, f, 5) for f in res}
 
     nodes = wl.nx * wl.ny
-    ach = bytes_per_node(head) * nodes / (res[head]["kernel_ms"] * 1e-3) / 1e9
-    roofline = dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    prof = profile_figures()
+    fresh = prof.get("source_sha256") == kernel_sources_digest() and \
+        prof.get("size") == str(args.size)
+    t_step = res[head]["kernel_ms"] * 1e-3
+    flops = float(prof.get(f"{head}.fp64_flops_per_node", "nan"))
+    valu = float(prof.get(f"{head}.valu_insts_per_node", "nan"))
+    traffic = None
+    if fresh:
+        traffic = round(float(prof[f"{head}.fetch_bytes_per_launch"]) +
+                        float(prof[f"{head}.write_bytes_per_launch"]))
+    ach = flops * nodes / t_step / 1e12
+    hbm = bytes_per_node(head) * nodes / t_step / 1e9
+    roofline = dict(bound="alu", achieved=round(ach, 2), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(ach / FP64_PEAK_TFLOPS, 4), traffic=traffic,
+                    kernel="step_kernel", fp64_flops_per_node=flops,
+                    counters_match_kernel=fresh,
+                    valu_issue_frac=round(valu * nodes / t_step / VALU_ISSUE_PEAK, 4),
+                    hbm=dict(achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                             frac=round(hbm / HBM_PEAK_GBS, 4),
+                             bytes_per_node=bytes_per_node(head)))
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
