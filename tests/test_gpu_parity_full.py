@@ -1,0 +1,141 @@
+"""Parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times: the GPU runs the whole grid; the oracle runs
+periodic crops centred on sampled nodes, wide enough that the crop's seam
+cannot reach the centre within the steps taken (a node's state after s steps
+depends on nodes at most s * (3 + |U| + 1) away: pull reach plus the
+central-difference stencil of a rebuilt link), and the centre nodes are
+compared.  Bounds as in test_gpu_parity (FP64 1e-12; FP32 1e-5, or with the
+sensor on 1e-3 per node and 1e-5 on the median)."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REACH = 3 + 4 + 1      # |U| <= 4 in these workloads (|u| < 3.75)
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2009_13426_amd as lbm
+    return lbm
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def sample_centres(wl, count, seed):
+    """Seeded sample: half near the lines where the initial quadrants meet
+    (and the periodic seam), where waves and lattice interfaces are; half
+    anywhere."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pts = []
+    for k in range(count):
+        if k % 2 == 0:
+            line = rng.integers(0, 2)
+            pos = rng.choice([0, wl.nx // 2]) + rng.integers(-4, 5)
+            other = rng.integers(0, wl.nx)
+            x, y = (pos, other) if line == 0 else (other, pos)
+        else:
+            x, y = rng.integers(0, wl.nx), rng.integers(0, wl.ny)
+        pts.append((int(x) % wl.nx, int(y) % wl.ny))
+    return pts
+
+
+def gpu_values(lbm, wl, steps, precision, pts):
+    import torch
+    sim = lbm.Sim.from_workload(wl, precision=precision)
+    sim.step(steps)
+    m = sim.macros()
+    ys = torch.tensor([p[1] for p in pts], device=m["rho"].device)
+    xs = torch.tensor([p[0] for p in pts], device=m["rho"].device)
+    out = {k: m[k][ys, xs].cpu().numpy() for k in ("rho", "ux", "uy", "T")}
+    sim.close()
+    del m
+    torch.cuda.empty_cache()
+    return out
+
+
+def oracle_values(orc, wl, steps, pts):
+    half = steps * REACH + 8
+    out = {k: [] for k in ("rho", "ux", "uy", "T", "Ucx", "Ucy")}
+    for (x, y) in pts:
+        crop = wl.window(x, y, half)
+        s = orc.Sim.from_workload(crop)
+        s.step(steps)
+        m = s.macros()
+        for k in out:
+            out[k].append(m[k][half, half])
+    return {k: np.array(v) for k, v in out.items()}
+
+
+def compare(got, ref, precision, sensor, what):
+    u_scale = np.max(np.hypot(ref["ux"], ref["uy"]))
+    e = np.maximum.reduce([np.abs(got["rho"] - ref["rho"]) / np.abs(ref["rho"]),
+                           np.abs(got["T"] - ref["T"]) / np.abs(ref["T"]),
+                           np.hypot(got["ux"] - ref["ux"], got["uy"] - ref["uy"]) / u_scale])
+    print(f"{what}: per-node max rel err {e.max():.2e}, median {np.median(e):.2e}", flush=True)
+    if precision == "fp64":
+        assert e.max() <= 1e-12, (what, e.max())
+    elif sensor:
+        assert e.max() <= 1e-3 and np.median(e) <= 1e-5, (what, e.max(), np.median(e))
+    else:
+        assert e.max() <= 1e-5, (what, e.max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_quadrant_4096_sampled(lbm, orc, precision):
+    steps = 6
+    wl = W.four_quadrant(4096, steps)
+    pts = sample_centres(wl, 16, seed=11)
+    print(f"quadrant 4096^2 {precision}, {steps} steps, {len(pts)} sampled nodes", flush=True)
+    got = gpu_values(lbm, wl, steps, precision, pts)
+    ref = oracle_values(orc, wl, steps, pts)
+    compare(got, ref, precision, wl.sensor, f"quadrant_4096/{precision}")
+
+
+_VORTEX_REF = {}
+
+
+def _vortex_oracle(orc, steps, c, half):
+    """The oracle's crop run, shared by the two precisions."""
+    key = (steps, c, half)
+    if key not in _VORTEX_REF:
+        s = orc.Sim.from_workload(W.config2(1024, steps).window(c, c, half))
+        s.step(steps)
+        _VORTEX_REF[key] = s.macros()
+    return _VORTEX_REF[key]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vortex_1024_block(lbm, orc, precision):
+    """The vortex field is smooth, so a crop's seam must sit where the field
+    is uniform: one crop of half-width 320 centred on the vortex (its seam
+    where the perturbation is below 1e-4), and every node of the central
+    block that the seam cannot reach within the steps taken is compared."""
+    import torch
+    steps = 10
+    wl = W.config2(1024, steps)
+    c, half = 512, 320
+    inner = half - steps * REACH - 8
+    print(f"vortex 1024^2 {precision}, {steps} steps, block of {(2 * inner + 1) ** 2} nodes", flush=True)
+    sim = lbm.Sim.from_workload(wl, precision=precision)
+    sim.step(steps)
+    m = sim.macros()
+    sl = slice(c - inner, c + inner + 1)
+    got = {k: m[k][sl, sl].cpu().numpy() for k in ("rho", "ux", "uy", "T")}
+    sim.close()
+    del m
+    torch.cuda.empty_cache()
+    rm = _vortex_oracle(orc, steps, c, half)
+    isl = slice(half - inner, half + inner + 1)
+    ref = {k: rm[k][isl, isl] for k in ("rho", "ux", "uy", "T")}
+    compare({k: v.ravel() for k, v in got.items()}, {k: v.ravel() for k, v in ref.items()},
+            precision, wl.sensor, f"vortex_1024/{precision}")
