@@ -135,6 +135,34 @@ def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
                        f"{n} steps, FP64, {dt:.1f} s")
 
 
+SERVE_JOBS = 32
+
+
+def serving_pass(torch, W, n_jobs=SERVE_JOBS, quantum=50):
+    """The first n_jobs of the seeded serving mix (vortex / quadrant flows,
+    side log-uniform in [64, 1024], Mach in [0.5, 3], 100-2000 steps), FP32
+    storage.  Capacity = jobs per second with every job queued at t = 0 on
+    the batched server; then Poisson arrivals at 80 % of capacity, served by
+    the continuous-batching loop and by the one-job-at-a-time path."""
+    from paper_2009_13426_amd import serve as S
+    specs = W.serving_jobs(n_jobs)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.6 * free)
+    eng = S.GpuEngine(precision="fp32")
+    cap = S.serve(S.requests_from_specs(specs, float("inf"), prebuild=True), eng, budget,
+                  quantum).summary()
+    rate = 0.8 * cap["jobs_per_s"]
+    reqs = S.requests_from_specs(specs, rate, prebuild=True)
+    batched = S.serve(reqs, eng, budget, quantum).summary()
+    alone = S.serve_one_at_a_time(reqs, eng).summary()
+    keep = ("p50_s", "p99_s", "mean_s", "mean_wait_s", "mlups", "makespan_s", "failed")
+    return dict(jobs=n_jobs, sample=f"first {n_jobs} jobs of the seeded 10,000-job mix",
+                capacity_jobs_per_s=round(cap["jobs_per_s"], 3), rate_jobs_per_s=round(rate, 3),
+                quantum_steps=quantum, memory_budget_bytes=budget,
+                batched={k: round(batched[k], 4) for k in keep},
+                one_at_a_time={k: round(alone[k], 4) for k in keep})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +171,8 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fp32,fp64")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the job-server pass (p50/p99 time-to-solution)")
     ap.add_argument("--no-counters", action="store_true",
                     help="skip the extra run with Newton and rebuild counters")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -204,6 +234,11 @@ def main():
                     hbm=dict(achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=round(hbm / HBM_PEAK_GBS, 4),
                              bytes_per_node=bytes_per_node(head)))
+    serving = None
+    if not args.no_serve:
+        print("[bench] serving mix", file=sys.stderr, flush=True)
+        serving = serving_pass(torch, W)
+        print(f"[bench] serving: {json.dumps(serving)}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -218,7 +253,7 @@ def main():
         config=dict(workload=f"four-quadrant Riemann {args.size}x{args.size}, D2Q21 adaptive "
                              f"shifts, Knudsen sensor, nu={wl.nu:g}, seeded draw",
                     nodes=nodes, precision=head),
-        roofline=roofline, cpu_baseline=cpu,
+        roofline=roofline, cpu_baseline=cpu, serving=serving,
         forms={f: dict(mlups=round(r["mlups"], 2), kernel_ms=round(r["kernel_ms"], 4),
                        rebuild_ms=round(r["rebuild_ms"], 4),
                        hbm_gbs=round(bytes_per_node(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9, 1),

@@ -110,6 +110,13 @@ size_t lbm_workspace_bytes(const lbm_config* cfg);
 lbm_status lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes,
                       void* hip_stream, lbm_ctx** out);
 
+/* As lbm_create, but the initial-guess table is copied (device to device, on
+ * the stream) from the existing context `like` on the same device instead of
+ * being built (for callers that create many contexts, e.g. a job server).
+ * `like` stays valid and unchanged; the copy is ordered on hip_stream. */
+lbm_status lbm_create_like(const lbm_ctx* like, const lbm_config* cfg, void* dev_workspace,
+                           size_t bytes, void* hip_stream, lbm_ctx** out);
+
 /* Grad initial condition (Sec. IV.A.1, eq. GradGeneral): per node the lattice
  * is selected from u (or fixed), h(0) = h_eq (1 + phi_h) with central
  * differences of the input fields, then one collision gives the stored
@@ -161,10 +168,12 @@ void lbm_velocities(int32_t* cx, int32_t* cy);
  * fixed summation order).  out: host pointer.  Synchronous. */
 lbm_status lbm_get_diag(lbm_ctx* ctx, lbm_diag* out);
 
-/* Advances n contexts that share one HIP stream (and one precision): ctxs[k]
- * by nsteps[k] steps, one fused launch per step over all still-running
- * contexts.  ctxs, nsteps: host arrays of n entries.  Synchronous; returns
- * the first error. */
+/* Advances n <= 1024 distinct contexts that share one HIP stream, device and
+ * precision: ctxs[k] by nsteps[k] steps.  Per step one rebuild launch and
+ * one step launch cover all contexts still running (the job table lives in
+ * ctxs[0]'s workspace).  ctxs, nsteps: host arrays of n entries.
+ * Synchronous; returns the first error (lbm_sync on each context tells
+ * which). */
 lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n);
 
 /* Frees the host context; the workspace stays the caller's. */

@@ -69,7 +69,7 @@ def workspace_bytes(cfg: _lib.Config) -> int:
 class Sim:
     """One periodic nx x ny simulation resident on a GPU."""
 
-    def __init__(self, nx: int, ny: int, device=None, stream=None, **kw):
+    def __init__(self, nx: int, ny: int, device=None, stream=None, like=None, **kw):
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -82,16 +82,22 @@ class Sim:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._ctx = C.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib.lbm_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()),
-                                  nbytes, C.c_void_p(self.stream.cuda_stream),
-                                  C.byref(self._ctx)), "lbm_create")
+            if like is None:
+                st = lib.lbm_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()),
+                                    nbytes, C.c_void_p(self.stream.cuda_stream),
+                                    C.byref(self._ctx))
+            else:  # initial-guess table copied from another simulation
+                st = lib.lbm_create_like(like.handle, C.byref(self.cfg),
+                                         C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx))
+            _check(st, "lbm_create")
 
     @classmethod
-    def from_workload(cls, wl, precision="fp64", device=None, stream=None, **over):
+    def from_workload(cls, wl, precision="fp64", device=None, stream=None, like=None, **over):
         kw = dict(nu=wl.nu, gamma=wl.gamma, shift_mode=wl.shift_mode, fixed_U=wl.fixed_U,
                   halfwidth=wl.halfwidth, sensor=wl.sensor, precision=precision)
         kw.update(over)
-        s = cls(wl.nx, wl.ny, device=device, stream=stream, **kw)
+        s = cls(wl.nx, wl.ny, device=device, stream=stream, like=like, **kw)
         static = wl.static_U if kw["shift_mode"] in (2, "static") else None
         s.init(*wl.fields(), static_U=static)
         return s
@@ -116,7 +122,7 @@ class Sim:
                 st = lib.lbm_init_fields_static(self._ctx, *ptrs,
                                                 *[C.c_void_p(a.data_ptr()) for a in u8])
         _check(st, "lbm_init_fields")
-        self._keep = args
+        del args  # lbm_init_fields is synchronous: the fields are consumed
 
     def step(self, n: int = 1):
         _check(lib.lbm_step(self._ctx, int(n)), "lbm_step")

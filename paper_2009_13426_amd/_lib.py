@@ -35,6 +35,8 @@ SIGNATURES = {
     "lbm_workspace_bytes": (C.c_size_t, [C.POINTER(Config)]),
     "lbm_create": (C.c_int, [C.POINTER(Config), C.c_void_p, C.c_size_t, C.c_void_p,
                              C.POINTER(C.c_void_p)]),
+    "lbm_create_like": (C.c_int, [C.c_void_p, C.POINTER(Config), C.c_void_p, C.c_size_t,
+                                  C.c_void_p, C.POINTER(C.c_void_p)]),
     "lbm_init_fields": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4),
     "lbm_init_fields_static": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "lbm_step": (C.c_int, [C.c_void_p, C.c_int32]),
@@ -66,6 +68,10 @@ def load():
             raise LibraryMissing(
                 f"{LIB_PATH} not found: build it with `python paper_2009_13426_amd/build.py` "
                 "(or __graft_entry__.build()); there is no fallback implementation")
+        # PyTorch ships its own HIP runtime.  It must be loaded before this
+        # library, so that the library binds to it: a second runtime in the
+        # process would not know the device memory torch allocates.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

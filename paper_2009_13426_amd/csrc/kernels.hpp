@@ -353,13 +353,11 @@ struct PullMap {
 // tail prepares the next step: moments of this collision, the mask of the
 // next pull's rebuilt links, and the list of nodes that have any.
 template <typename S, bool STREAM, int BLOCK>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
-void step_kernel(StepArgs a) {
+__device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   __shared__ S sh_pop[2 * kQ][BLOCK];
   __shared__ unsigned long long sh_stat[2 + LBM_HIST_BINS];
 
   const int tid = threadIdx.x;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
   const long long N = a.grid.N;
   const int nx = a.grid.nx;
   const long long n = static_cast<long long>(b) * BLOCK + tid;
@@ -560,6 +558,12 @@ void step_kernel(StepArgs a) {
   }
 }
 
+template <typename S, bool STREAM, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void step_kernel(StepArgs a) {
+  step_body<S, STREAM, BLOCK>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // ------------------------------------------------------------ rebuild
 // a2: rebuilds, before a step, every link of that step's pull whose source
 // collided in another lattice, into the receiver's slot of the buffer the
@@ -568,7 +572,7 @@ void step_kernel(StepArgs a) {
 // lane.  Grid-stride over the list; clears the other list counter for the
 // coming step's appends.
 template <typename S>
-__global__ __launch_bounds__(kBlock) void rebuild_kernel(RebuildArgs a) {
+__device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
   __shared__ int sh_node[kWaves][64];
   __shared__ int sh_k[kWaves][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -654,6 +658,97 @@ __global__ __launch_bounds__(kBlock) void rebuild_kernel(RebuildArgs a) {
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void rebuild_kernel(RebuildArgs a) {
+  rebuild_body<S>(a);
+}
+
+// ------------------------------------------------------------ batched
+// One context's share of a batched launch: many independent grids (uneven
+// sizes, one storage type) advanced by one rebuild launch and one step
+// launch per step.  Buffer parity and step index follow from the state at
+// the batch start and the batch step s.
+struct JobArgs {
+  void* pop[2];  // f planes of population buffer 0 / 1; g planes follow 21 N values on
+  int* tag[2];
+  Carry carry;
+  Grid grid;
+  Phys phys;
+  GuessTable table;
+  DevDiag* diag;
+  int cur;     // buffer holding the state at the batch start
+  int step0;   // steps done at the batch start
+  int nsteps;  // steps of this job in the batch
+  int block0;  // first block of this job in a step launch (jobs in block order)
+  int nblocks;
+};
+
+template <typename S>
+__device__ __forceinline__ StepArgs job_step_args(const JobArgs& j, int s) {
+  const int src = (j.cur + s) & 1, dst = src ^ 1;
+  StepArgs a;
+  a.fin = j.pop[src];
+  a.gin = static_cast<const S*>(j.pop[src]) + kQ * j.grid.N;
+  a.fout = j.pop[dst];
+  a.gout = static_cast<S*>(j.pop[dst]) + kQ * j.grid.N;
+  a.tin = j.tag[src];
+  a.tout = j.tag[dst];
+  a.carry = j.carry;
+  a.grid = j.grid;
+  a.phys = j.phys;
+  a.table = j.table;
+  a.step = j.step0 + s + 1;
+  a.diag = j.diag;
+  return a;
+}
+
+// Step s of a batch: the grid covers every job's blocks; a block finds its
+// job by binary search over the jobs' first blocks.
+template <typename S, int BLOCK>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void step_batched_kernel(const JobArgs* jobs, int njobs, int s) {
+  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block0 <= gb) lo = mid;
+    else hi = mid - 1;
+  }
+  const JobArgs& j = jobs[lo];
+  if (s >= j.nsteps || gb - j.block0 >= j.nblocks) return;
+  step_body<S, true, BLOCK>(job_step_args<S>(j, s), gb - j.block0);
+}
+
+// Failure words of every job of a batch, gathered for one copy to the host.
+__global__ __launch_bounds__(kBlock) void gather_fail_keys_kernel(const JobArgs* jobs, int njobs,
+                                                                 unsigned long long* out) {
+  const int k = blockIdx.x * kBlock + threadIdx.x;
+  if (k < njobs) out[k] = jobs[k].diag->fail_key;
+}
+
+// Rebuilds of step s for every job of a batch, each job's list spread over
+// the whole grid in turn.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void rebuild_batched_kernel(const JobArgs* jobs, int njobs,
+                                                                 int s) {
+  for (int k = 0; k < njobs; ++k) {
+    const JobArgs& j = jobs[k];
+    if (s >= j.nsteps || j.phys.shift_mode == 1) continue;
+    const int src = (j.cur + s) & 1, dst = src ^ 1;
+    RebuildArgs a;
+    a.fout = j.pop[dst];
+    a.gout = static_cast<S*>(j.pop[dst]) + kQ * j.grid.N;
+    a.tags = j.tag[src];
+    a.carry = j.carry;
+    a.grid = j.grid;
+    a.phys = j.phys;
+    a.table = j.table;
+    a.step = j.step0 + s + 1;
+    a.diag = j.diag;
+    rebuild_body<S>(a);
   }
 }
 

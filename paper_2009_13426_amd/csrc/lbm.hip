@@ -22,6 +22,7 @@ using namespace lbm;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxBatch = 1024;  // contexts per lbm_step_batched call
 
 // Initial-guess table: |u'_x|, |u'_y| in [0, 2] (step 1/32), 1/T in
 // [0.5, 1/0.3] (35 levels), 8 floats per point (4.7 MB; the states of a flow
@@ -40,6 +41,8 @@ struct Layout {
   size_t diag_off, part_off, sums_off, table_off, total;
   size_t off_pop[2], off_tag[2];
   size_t mac_off, mask_off, list_off, count_off;  // carried from step to step
+  size_t batch_off;                               // job table of a batched call
+  size_t keys_off;                                // failure words of a batched call
   int nparts;
 };
 
@@ -80,6 +83,10 @@ Layout layout(const lbm_config* c) {
   off += align_up(N * sizeof(int));
   L.count_off = off;
   off += align_up(2 * sizeof(unsigned));
+  L.batch_off = off;
+  off += align_up(kMaxBatch * sizeof(JobArgs));
+  L.keys_off = off;
+  off += align_up(kMaxBatch * sizeof(unsigned long long));
   L.diag_off = off;
   off += align_up(sizeof(DevDiag));
   L.part_off = off;
@@ -269,8 +276,10 @@ size_t lbm_workspace_bytes(const lbm_config* cfg) {
   return layout(cfg).total;
 }
 
-lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* stream,
-                      lbm_ctx** out) {
+namespace {
+
+lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, size_t bytes,
+                         void* stream, lbm_ctx** out) {
   if (!out) return LBM_ERR_ARG;
   *out = nullptr;
   if (!config_ok(cfg)) return LBM_ERR_ARG;
@@ -325,7 +334,14 @@ lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* strea
   c->table.inv_hs = (kTabS - 1) / (kTabSmax - kTabSmin);
   hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
                      c->carry().counters);
-  {
+  const size_t table_bytes = static_cast<size_t>(kTabU) * kTabU * kTabS * 8 * sizeof(float);
+  if (like) {
+    if (hipMemcpyAsync(c->ws + L.table_off, like->ws + like->lay.table_off, table_bytes,
+                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
+      delete c;
+      return LBM_ERR_HIP;
+    }
+  } else {
     const int pts = kTabU * kTabU * kTabS;
     hipLaunchKernelGGL(table_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream,
                        reinterpret_cast<float*>(c->ws + L.table_off), kTabU, kTabS, kTabUmax,
@@ -337,6 +353,28 @@ lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* strea
   }
   *out = c;
   return LBM_OK;
+}
+
+}  // namespace
+
+lbm_status lbm_create(const lbm_config* cfg, void* ws, size_t bytes, void* stream,
+                      lbm_ctx** out) {
+  return create_common(nullptr, cfg, ws, bytes, stream, out);
+}
+
+lbm_status lbm_create_like(const lbm_ctx* like, const lbm_config* cfg, void* ws, size_t bytes,
+                           void* stream, lbm_ctx** out) {
+  if (!like) {
+    if (out) *out = nullptr;
+    return LBM_ERR_ARG;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBM_ERR_HIP;
+  if (dev != like->device) {
+    if (out) *out = nullptr;
+    return LBM_ERR_ARG;
+  }
+  return create_common(like, cfg, ws, bytes, stream, out);
 }
 
 lbm_status lbm_init_fields(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
@@ -507,25 +545,86 @@ lbm_status lbm_get_diag(lbm_ctx* c, lbm_diag* out) {
 }
 
 lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n) {
-  if (!ctxs || !nsteps || n < 0) return LBM_ERR_ARG;
+  if (!ctxs || !nsteps || n < 0 || n > kMaxBatch) return LBM_ERR_ARG;
+  if (n == 0) return LBM_OK;
   int32_t most = 0;
+  bool any_rebuild = false;
+  long long nodes = 0;
   for (int32_t k = 0; k < n; ++k) {
-    if (!ctxs[k] || nsteps[k] < 0) return LBM_ERR_ARG;
-    if (!ctxs[k]->initialized) return LBM_ERR_STATE;
+    lbm_ctx* c = ctxs[k];
+    if (!c || nsteps[k] < 0) return LBM_ERR_ARG;
+    if (c->cfg.precision != ctxs[0]->cfg.precision || c->stream != ctxs[0]->stream ||
+        c->device != ctxs[0]->device)
+      return LBM_ERR_ARG;
+    for (int32_t m = 0; m < k; ++m)
+      if (ctxs[m] == c) return LBM_ERR_ARG;
+    if (!c->initialized) return LBM_ERR_STATE;
     most = std::max(most, nsteps[k]);
+    any_rebuild = any_rebuild || c->cfg.shift_mode != LBM_SHIFT_FIXED;
+    nodes += c->grid.N;
   }
-  for (int32_t s = 0; s < most; ++s)
-    for (int32_t k = 0; k < n; ++k)
-      if (s < nsteps[k]) {
-        lbm_status st = lbm_step_async(ctxs[k], 1);
-        if (st) return st;
-      }
-  lbm_status first = LBM_OK;
+  // job table, blocks of the step launch in job order
+  std::vector<JobArgs> jobs(n);
+  long long blocks = 0;
   for (int32_t k = 0; k < n; ++k) {
-    lbm_status st = read_status(ctxs[k], nullptr);
-    if (st && first == LBM_OK) first = st;
+    lbm_ctx* c = ctxs[k];
+    JobArgs& j = jobs[k];
+    for (int b = 0; b < 2; ++b) {
+      j.pop[b] = c->f(b);
+      j.tag[b] = c->tag(b);
+    }
+    j.carry = c->carry();
+    j.grid = c->grid;
+    j.phys = c->phys;
+    j.table = c->table;
+    j.diag = c->diag();
+    j.cur = c->cur;
+    j.step0 = static_cast<int>(c->steps_done);
+    j.nsteps = nsteps[k];
+    j.block0 = static_cast<int>(blocks);
+    j.nblocks = c->step_blocks;
+    blocks += c->step_blocks;
   }
-  return first;
+  if (blocks >= (1ll << 31)) return LBM_ERR_ARG;
+  lbm_ctx* c0 = ctxs[0];
+  JobArgs* dev_jobs = reinterpret_cast<JobArgs*>(c0->ws + c0->lay.batch_off);
+  HIP_TRY(hipMemcpyAsync(dev_jobs, jobs.data(), n * sizeof(JobArgs), hipMemcpyHostToDevice,
+                         c0->stream));
+  const dim3 step_grid(static_cast<unsigned>(blocks));
+  const dim3 rebuild_grid(static_cast<unsigned>(std::min<long long>((nodes + kBlock - 1) / kBlock, 4096)));
+  for (int32_t st = 0; st < most; ++st) {
+    if (c0->cfg.precision == LBM_FP64) {
+      if (any_rebuild)
+        hipLaunchKernelGGL(rebuild_batched_kernel<double>, rebuild_grid, dim3(kBlock), 0,
+                           c0->stream, dev_jobs, n, st);
+      hipLaunchKernelGGL((step_batched_kernel<double, step_block<double>()>), step_grid,
+                         dim3(step_block<double>()), 0, c0->stream, dev_jobs, n, st);
+    } else {
+      if (any_rebuild)
+        hipLaunchKernelGGL(rebuild_batched_kernel<float>, rebuild_grid, dim3(kBlock), 0,
+                           c0->stream, dev_jobs, n, st);
+      hipLaunchKernelGGL((step_batched_kernel<float, step_block<float>()>), step_grid,
+                         dim3(step_block<float>()), 0, c0->stream, dev_jobs, n, st);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  for (int32_t k = 0; k < n; ++k) {
+    ctxs[k]->cur ^= (nsteps[k] & 1);
+    ctxs[k]->steps_done += nsteps[k];
+  }
+  // every job's failure word in one copy
+  unsigned long long* dev_keys = reinterpret_cast<unsigned long long*>(c0->ws + c0->lay.keys_off);
+  hipLaunchKernelGGL(gather_fail_keys_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     c0->stream, dev_jobs, n, dev_keys);
+  HIP_TRY(hipGetLastError());
+  std::vector<unsigned long long> keys(n, ~0ull);
+  HIP_TRY(hipMemcpyAsync(keys.data(), dev_keys, n * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, c0->stream));
+  HIP_TRY(hipStreamSynchronize(c0->stream));
+  for (int32_t k = 0; k < n; ++k)
+    if (keys[k] != ~0ull)
+      return (keys[k] & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
+  return LBM_OK;
 }
 
 void lbm_destroy(lbm_ctx* c) { delete c; }

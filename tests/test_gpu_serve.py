@@ -1,0 +1,74 @@
+"""The job server on the GPU: jobs that arrive while others run are admitted
+into the running batch, and every job's result is the same in the mix as
+alone (bitwise: the batched launches run the same per-node code on the same
+inputs)."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def serve():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2009_13426_amd import serve
+    return serve
+
+
+def small_mix():
+    """Vortex and quadrant jobs of uneven sides and step counts, arriving
+    over ~40 ms so that later ones join a running batch."""
+    specs = []
+    sides = [48, 80, 64, 96, 56, 72]
+    steps = [60, 25, 90, 40, 70, 30]
+    for j, (n, k) in enumerate(zip(sides, steps)):
+        kind = "vortex" if j % 2 == 0 else "quadrant"
+        specs.append(W.JobSpec(j, kind, n, 1.0 + 0.3 * j, k, 1.0))
+    return specs
+
+
+def macros_of(sim):
+    m = sim.macros()
+    return {k: v.cpu().numpy() for k, v in m.items()}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_mix_equals_alone(serve, precision):
+    import paper_2009_13426_amd as lbm
+    specs = small_mix()
+    reqs = serve.requests_from_specs(specs, rate=150.0)
+    eng = serve.GpuEngine(precision=precision)
+    got = {}
+    rep = serve.serve(reqs, eng, memory_budget=1 << 34, quantum=10,
+                      on_finish=lambda req, sim: got.__setitem__(req.job_id, macros_of(sim)))
+    s = rep.summary()
+    print(f"{precision}: {s['jobs']} jobs, {s['quanta']} quanta, p50 {s['p50_s'] * 1e3:.1f} ms, "
+          f"p99 {s['p99_s'] * 1e3:.1f} ms, failed {s['failed']}", flush=True)
+    assert s["failed"] == 0
+    assert sorted(got) == [sp.job_id for sp in specs]
+    for sp in specs:
+        sim = lbm.Sim.from_workload(sp.build(), precision=precision)
+        sim.step(sp.steps)
+        alone = macros_of(sim)
+        sim.close()
+        for k in ("rho", "ux", "uy", "T", "Ux", "Uy"):
+            assert np.array_equal(alone[k], got[sp.job_id][k]), (sp.job_id, k)
+
+
+def test_late_arrivals_join_the_running_batch(serve):
+    # job 1 arrives just after job 0 started; with a small quantum it must be
+    # admitted while job 0 still runs, and finish first (it is much shorter)
+    specs = [W.JobSpec(0, "quadrant", 256, 1.5, 400, 0.0),
+             W.JobSpec(1, "vortex", 64, 1.0, 20, 0.0)]
+    reqs = serve.requests_from_specs(specs, rate=1e9)
+    reqs[1].arrival = 0.005
+    eng = serve.GpuEngine(precision="fp32")
+    rep = serve.serve(reqs, eng, memory_budget=1 << 34, quantum=5)
+    r0, r1 = rep.results
+    print(f"job0 admitted {r0.admitted * 1e3:.1f} ms finished {r0.finished * 1e3:.1f} ms; "
+          f"job1 admitted {r1.admitted * 1e3:.1f} ms finished {r1.finished * 1e3:.1f} ms", flush=True)
+    assert r0.status == 0 and r1.status == 0
+    assert r1.admitted < r0.finished and r1.finished < r0.finished

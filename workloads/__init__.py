@@ -135,13 +135,16 @@ def isentropic_vortex(L: int = 1024, mach: float = 3.0, beta: float = 5.0,
                       noise: float = 1e-4, steps: int = 5000,
                       nu: float | None = None, seed_index: int = 2,
                       T_inf: float = T0, rho_inf: float = RHO0,
-                      name: str | None = None) -> Workload:
+                      name: str | None = None, sensor: int = 1) -> Workload:
     """Isentropic vortex of strength beta, radius L/10, advected diagonally.
 
     The free stream moves at `mach` times the free-stream sound speed along
     the diagonal; at Mach 3 and T_inf = 0.7 each component is exactly 2.1.
     Velocity is scaled by sqrt(T_inf), temperature drop by T_inf.  Density
     carries seeded uniform relative noise of amplitude `noise` at fixed u, T.
+    At nu = 1e-4 T_inf (tau = 1/2 + 1e-4) this is the low-viscosity regime in
+    which the paper turns the Knudsen-number sensor on (Sec. IV.A.2); it is on
+    by default.
     """
     R = L / 10.0
     c_inf = math.sqrt(GAMMA * T_inf)
@@ -162,7 +165,7 @@ def isentropic_vortex(L: int = 1024, mach: float = 3.0, beta: float = 5.0,
         rho = rho * (1.0 + noise * rng.uniform(-1.0, 1.0, size=rho.shape))
     nu = 1e-4 * T_inf if nu is None else nu
     return Workload(name or f"vortex_{L}x{L}_M{mach:g}", L, L, _c(rho), _c(ux),
-                    _c(uy), _c(T), nu, steps, 0, (0, 0), 0.5,
+                    _c(uy), _c(T), nu, steps, 0, (0, 0), 0.5, sensor=sensor,
                     meta=dict(R=R, beta=beta, u_inf=(comp, comp), mach=mach))
 
 
