@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 CASES = {
     # name: (workload, steps, bound on the max error, bound on the L1 error)
     "C0_sod_256x1": (lambda: W.config0(), 200, 1e-5, 1e-6),
-    "C1_advected_sod_2048x4": (lambda: W.config1(2048, 4, 250), 250, 1e-3, 1e-5),
+    "C1_advected_sod_2048x4": (lambda: W.config1(2048, 4, 2000), 2000, 2e-1, 3e-3),
     "C2_vortex_1024": (lambda: W.config2(1024, 5000), 5000, 3e-2, 3e-3),
     "C3_quadrant_4096": (lambda: W.config3(4096, 1000), 1000, 2e-1, 3e-3),
 }

@@ -76,14 +76,14 @@ def oracle_values(orc, wl, steps, pts):
     return {k: np.array(v) for k, v in out.items()}
 
 
-def compare(got, ref, precision, sensor, what):
+def compare(got, ref, precision, sensor, what, fp64_bounds=(1e-12, 1e-12)):
     u_scale = np.max(np.hypot(ref["ux"], ref["uy"]))
     e = np.maximum.reduce([np.abs(got["rho"] - ref["rho"]) / np.abs(ref["rho"]),
                            np.abs(got["T"] - ref["T"]) / np.abs(ref["T"]),
                            np.hypot(got["ux"] - ref["ux"], got["uy"] - ref["uy"]) / u_scale])
     print(f"{what}: per-node max rel err {e.max():.2e}, median {np.median(e):.2e}", flush=True)
     if precision == "fp64":
-        assert e.max() <= 1e-12, (what, e.max())
+        assert e.max() <= fp64_bounds[0] and np.median(e) <= fp64_bounds[1], (what, e.max())
     elif sensor:
         assert e.max() <= 1e-3 and np.median(e) <= 1e-5, (what, e.max(), np.median(e))
     else:
@@ -142,3 +142,34 @@ def test_vortex_1024_block(lbm, orc, precision):
     ref = {k: rm[k][isl, isl] for k in ("rho", "ux", "uy", "T")}
     compare({k: v.ravel() for k, v in got.items()}, {k: v.ravel() for k, v in ref.items()},
             precision, wl.sensor, f"vortex_1024/{precision}")
+
+
+_C1_REF = {}
+
+
+@pytest.mark.parametrize("precision", ["fp64"])
+def test_advected_sod_2048x4_full(lbm, orc, precision):
+    """The whole 2048 x 4 grid after the configuration's 2000 steps, against
+    the oracle run on the same grid (shocks, lattice changes and the sensor
+    throughout; the FP32 form's error over this horizon is reported by
+    test_gpu_fp32_report).  Over this
+    horizon the shocks amplify the rounding differences of the two sides
+    (summation order, Newton paths) from ~1e-16 to ~3e-10 at the shocks
+    and ~1e-12 elsewhere, so the FP64 form is held to 1e-9 per node and
+    1e-11 on the median; over the 150-step horizon of test_gpu_parity the
+    1e-12 bound holds on every node."""
+    steps = 2000
+    wl = W.config1(2048, 4, steps)
+    if steps not in _C1_REF:
+        s = orc.Sim.from_workload(wl)
+        s.step(steps)
+        _C1_REF[steps] = s.macros()
+    ref = _C1_REF[steps]
+    sim = lbm.Sim.from_workload(wl, precision=precision)
+    sim.step(steps)
+    got = {k: v.cpu().numpy() for k, v in sim.macros().items()}
+    sim.close()
+    compare({k: got[k].ravel() for k in ("rho", "ux", "uy", "T")},
+            {k: ref[k].ravel() for k in ("rho", "ux", "uy", "T")},
+            precision, wl.sensor, f"advected_sod_2048x4/{precision}/{steps}",
+            fp64_bounds=(1e-9, 1e-11))
