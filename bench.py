@@ -13,9 +13,13 @@ Newton); the FP64 form is timed the same way and reported beside it.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--size L] [--no-cpu]
 
 One JSON line on stdout.  Inputs are resident on the GPU before timing
-starts; the timed region is K steps between two synchronisations, with HIP
-events around every launch on the stream the library launches on (the step
-kernel and the link-rebuild kernel are timed separately).
+starts.  The launch schedule is the autotuner's choice for the grid's size
+class (tuned and cached before any timing on a miss; --schedule default
+keeps the library's).  The timed region is K steps between two
+synchronisations, replayed as HIP graphs of --graph-chunk steps; a second
+pass of K steps with HIP events around every launch on the stream the
+library launches on gives the step kernel's and the link-rebuild kernel's
+own durations.
 
 The step kernel is bound by FP64 vector arithmetic (the Newton solve), so
 `roofline` is the ALU one: FP64 flops per node update (counted by rocprofv3
@@ -80,22 +84,30 @@ def profile_figures():
     return out
 
 
-def time_form(lbm, torch, wl, precision, steps, warmup):
-    """Timed region: `steps` steps between two synchronisations, HIP events
-    around every launch on the library's stream (step and link-rebuild
-    kernels timed separately)."""
-    sim = lbm.Sim.from_workload(wl, precision=precision)
-    sim.step(warmup)
+def time_form(lbm, torch, wl, precision, steps, warmup, schedule=None, chunk=10):
+    """Timed region: `steps` steps between two synchronisations, run as
+    replays of a HIP graph of `chunk` steps (lbm_step_graph_async; the graph
+    is built during the warm-up).  A second pass of `steps` steps with HIP
+    events around every launch on the library's stream gives the step and
+    link-rebuild kernels' own durations."""
+    sim = lbm.Sim.from_workload(wl, precision=precision, schedule=schedule)
+    sched = sim.schedule
+    graphed = warmup - warmup % chunk
+    if graphed:
+        sim.step_graph(graphed, chunk)
+    sim.step(warmup - graphed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms_rebuild, ms_step = sim.step_profiled(steps)
+    sim.step_graph_async(steps, chunk)
+    sim.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ms_rebuild, ms_step = sim.step_profiled(steps)
     d = sim.diag()
     nodes = wl.nx * wl.ny
     out = dict(ms_per_step=wall * 1e3 / steps, kernel_ms=ms_step / steps,
                rebuild_ms=ms_rebuild / steps, mlups=nodes * steps / wall / 1e6,
-               conserved=d["conserved"], status=d["status"])
+               conserved=d["conserved"], status=d["status"], schedule=sched)
     sim.close()
     return out
 
@@ -138,7 +150,7 @@ def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
 SERVE_JOBS = 32
 
 
-def serving_pass(torch, W, n_jobs=SERVE_JOBS, quantum=50):
+def serving_pass(torch, W, n_jobs=SERVE_JOBS, quantum=50, schedule="auto"):
     """The first n_jobs of the seeded serving mix (vortex / quadrant flows,
     side log-uniform in [64, 1024], Mach in [0.5, 3], 100-2000 steps), FP32
     storage.  Capacity = jobs per second with every job queued at t = 0 on
@@ -148,7 +160,8 @@ def serving_pass(torch, W, n_jobs=SERVE_JOBS, quantum=50):
     specs = W.serving_jobs(n_jobs)
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.6 * free)
-    eng = S.GpuEngine(precision="fp32")
+    eng = S.GpuEngine(precision="fp32", schedule=schedule)
+    eng.prepare(S.requests_from_specs(specs, float("inf")))
     cap = S.serve(S.requests_from_specs(specs, float("inf"), prebuild=True), eng, budget,
                   quantum).summary()
     rate = 0.8 * cap["jobs_per_s"]
@@ -159,6 +172,7 @@ def serving_pass(torch, W, n_jobs=SERVE_JOBS, quantum=50):
     return dict(jobs=n_jobs, sample=f"first {n_jobs} jobs of the seeded 10,000-job mix",
                 capacity_jobs_per_s=round(cap["jobs_per_s"], 3), rate_jobs_per_s=round(rate, 3),
                 quantum_steps=quantum, memory_budget_bytes=budget,
+                batched_schedule=eng.batch_schedule,
                 batched={k: round(batched[k], 4) for k in keep},
                 one_at_a_time={k: round(alone[k], 4) for k in keep})
 
@@ -170,6 +184,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--schedule", default="auto", choices=("auto", "default"),
+                    help="launch schedule: the autotuner's choice for the grid's size class "
+                         "(cached; tuned before the timed region on a miss) or the library "
+                         "default")
+    ap.add_argument("--graph-chunk", type=int, default=10,
+                    help="steps per HIP graph replayed in the timed region (even)")
     ap.add_argument("--forms", default="fp32,fp64")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the job-server pass (p50/p99 time-to-solution)")
@@ -203,7 +223,12 @@ def main():
     for form in args.forms.split(","):
         print(f"[bench] timing {form} {args.size}^2, warmup {args.warmup}, steps {args.steps}",
               file=sys.stderr, flush=True)
-        res[form] = time_form(lbm, torch, wl, form, args.steps, args.warmup)
+        sched = None
+        if args.schedule == "auto":
+            from paper_2009_13426_amd import autotune
+            sched = autotune.schedule_for(form, args.size, args.size)
+        res[form] = time_form(lbm, torch, wl, form, args.steps, args.warmup, sched,
+                              args.graph_chunk)
         print(f"[bench] {form}: {res[form]['mlups']:.1f} MLUPS, step kernel "
               f"{res[form]['kernel_ms']:.3f} ms, rebuild kernel {res[form]['rebuild_ms']:.3f} ms",
               file=sys.stderr, flush=True)
@@ -237,7 +262,7 @@ def main():
     serving = None
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
-        serving = serving_pass(torch, W)
+        serving = serving_pass(torch, W, schedule="auto" if args.schedule == "auto" else None)
         print(f"[bench] serving: {json.dumps(serving)}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
@@ -252,10 +277,11 @@ def main():
         dtype="f32-store/f64-newton" if head == "fp32" else "f64", data="synthetic",
         config=dict(workload=f"four-quadrant Riemann {args.size}x{args.size}, D2Q21 adaptive "
                              f"shifts, Knudsen sensor, nu={wl.nu:g}, seeded draw",
-                    nodes=nodes, precision=head),
+                    nodes=nodes, precision=head, schedule=res[head]["schedule"],
+                    graph_chunk=args.graph_chunk),
         roofline=roofline, cpu_baseline=cpu, serving=serving,
         forms={f: dict(mlups=round(r["mlups"], 2), kernel_ms=round(r["kernel_ms"], 4),
-                       rebuild_ms=round(r["rebuild_ms"], 4),
+                       rebuild_ms=round(r["rebuild_ms"], 4), schedule=r["schedule"],
                        hbm_gbs=round(bytes_per_node(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9, 1),
                        bytes_per_node=bytes_per_node(f), **counters[f])
                for f, r in res.items()},

@@ -93,6 +93,20 @@ typedef struct {
   double conserved[4];       /* mass, x/y momentum, total energy of the current state */
 } lbm_diag;
 
+/* Launch schedule of a context's step loop.  Changing it changes how the
+ * nodes are spread over workgroups, never what a node computes: results
+ * are bitwise the same under every valid schedule. */
+typedef struct {
+  int32_t step_block;      /* lanes per workgroup of the step kernel: 64 or 128,
+                            * or 256 in FP32 storage (default 64) */
+  int32_t tiles_per_block; /* consecutive tiles of step_block nodes one workgroup
+                            * runs one after the other, 1..64 (default 1) */
+  int32_t xcd_remap;       /* 1: each XCD runs one contiguous range of tiles
+                            * (default); 0: tiles in dispatch order */
+  int32_t rebuild_blocks;  /* 256-lane workgroups of the link-rebuild launch,
+                            * 1..65535; 0: one per 256 nodes, at most 4096 (default) */
+} lbm_schedule;
+
 /* Fills cfg with the defaults used by the paper's tests: gamma 1.4, nu 0,
  * adaptive shifts with half-width 0.5, Newton tolerance 1e-12 and 30
  * iterations, |U| <= 6, FP64, no sensor, no counters. */
@@ -147,6 +161,34 @@ lbm_status lbm_step_async(lbm_ctx* ctx, int32_t nsteps);
  * lattice is fixed) and of the step launches.  Synchronous; for measurement. */
 lbm_status lbm_step_profiled(lbm_ctx* ctx, int32_t nsteps, double* ms_rebuild, double* ms_step);
 
+/* Copies the whole state of src into dst (populations of the current
+ * time level, lattice tags, the moments and rebuild lists carried to the
+ * next step, steps done, diagnostics), device to device: a checkpoint or a
+ * restore.  Both contexts must have the same configuration (every field of
+ * lbm_config) and device, and src must be initialised; else LBM_ERR_ARG or
+ * LBM_ERR_STATE.  Waits for src's stream, then copies on dst's stream and
+ * waits for it.  The initial-guess table is not copied (each context has
+ * its own, built or copied at creation).  dst's step graphs stay valid. */
+lbm_status lbm_copy_state(lbm_ctx* dst, const lbm_ctx* src);
+
+/* Sets the context's launch schedule (host struct, copied).  LBM_ERR_ARG
+ * for a field out of range; the previous schedule then stays.  Drops the
+ * context's step graphs (lbm_step_graph_async builds them again). */
+lbm_status lbm_set_schedule(lbm_ctx* ctx, const lbm_schedule* sched);
+
+/* The context's current schedule, with defaults resolved (rebuild_blocks is
+ * never 0 in the result).  sched: host pointer. */
+lbm_status lbm_get_schedule(const lbm_ctx* ctx, lbm_schedule* sched);
+
+/* As lbm_step_async, but full chunks of `chunk` steps (even, 2..1024) run as
+ * replays of a HIP graph holding the chunk's launches; the graph is built on
+ * first use for the context's buffer parity and kept until the schedule
+ * changes or the context is destroyed, and the remaining nsteps % chunk
+ * steps are plain launches.  Same results, bitwise, as lbm_step_async; a
+ * failure is reported with its true step.  The graph holds kernel nodes
+ * only (no memset or copy nodes). */
+lbm_status lbm_step_graph_async(lbm_ctx* ctx, int32_t nsteps, int32_t chunk);
+
 /* Waits for the context's stream and returns the device error status. */
 lbm_status lbm_sync(lbm_ctx* ctx);
 
@@ -171,7 +213,10 @@ lbm_status lbm_get_diag(lbm_ctx* ctx, lbm_diag* out);
 /* Advances n <= 1024 distinct contexts that share one HIP stream, device and
  * precision: ctxs[k] by nsteps[k] steps.  Per step one rebuild launch and
  * one step launch cover all contexts still running (the job table lives in
- * ctxs[0]'s workspace).  ctxs, nsteps: host arrays of n entries.
+ * ctxs[0]'s workspace).  The step launch takes step_block and xcd_remap
+ * from ctxs[0]'s schedule and runs one tile per workgroup; the rebuild
+ * launch spreads every context's list over at most 4096 workgroups.
+ * ctxs, nsteps: host arrays of n entries.
  * Synchronous; returns the first error (lbm_sync on each context tells
  * which). */
 lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n);

@@ -69,7 +69,11 @@ def workspace_bytes(cfg: _lib.Config) -> int:
 class Sim:
     """One periodic nx x ny simulation resident on a GPU."""
 
-    def __init__(self, nx: int, ny: int, device=None, stream=None, like=None, **kw):
+    def __init__(self, nx: int, ny: int, device=None, stream=None, like=None, schedule=None,
+                 **kw):
+        """schedule: None (library default), a dict of lbm_schedule fields,
+        or "auto" (the autotuner's cached choice for this size class,
+        tuned on a miss)."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -91,13 +95,20 @@ class Sim:
                                          C.c_void_p(self.workspace.data_ptr()), nbytes,
                                          C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx))
             _check(st, "lbm_create")
+        if schedule == "auto":
+            from . import autotune
+            schedule = autotune.schedule_for(kw.get("precision", "fp64"), nx, ny,
+                                             device=self.device)
+        if schedule:
+            self.schedule = schedule
 
     @classmethod
-    def from_workload(cls, wl, precision="fp64", device=None, stream=None, like=None, **over):
+    def from_workload(cls, wl, precision="fp64", device=None, stream=None, like=None,
+                      schedule=None, **over):
         kw = dict(nu=wl.nu, gamma=wl.gamma, shift_mode=wl.shift_mode, fixed_U=wl.fixed_U,
                   halfwidth=wl.halfwidth, sensor=wl.sensor, precision=precision)
         kw.update(over)
-        s = cls(wl.nx, wl.ny, device=device, stream=stream, like=like, **kw)
+        s = cls(wl.nx, wl.ny, device=device, stream=stream, like=like, schedule=schedule, **kw)
         static = wl.static_U if kw["shift_mode"] in (2, "static") else None
         s.init(*wl.fields(), static_U=static)
         return s
@@ -137,6 +148,33 @@ class Sim:
         _check(lib.lbm_step_profiled(self._ctx, int(n), C.byref(a), C.byref(b)),
                "lbm_step_profiled")
         return a.value, b.value
+
+    def copy_state_from(self, other: "Sim"):
+        """Device-to-device copy of `other`'s state into this simulation
+        (same configuration required): checkpoint / restore."""
+        _check(lib.lbm_copy_state(self._ctx, other.handle), "lbm_copy_state")
+
+    def step_graph(self, n: int, chunk: int = 32):
+        """n steps, full chunks as replays of a HIP graph of `chunk` steps
+        (lbm_step_graph_async), then waits and checks for errors."""
+        _check(lib.lbm_step_graph_async(self._ctx, int(n), int(chunk)), "lbm_step_graph_async")
+        self.sync()
+
+    def step_graph_async(self, n: int, chunk: int = 32):
+        _check(lib.lbm_step_graph_async(self._ctx, int(n), int(chunk)), "lbm_step_graph_async")
+
+    @property
+    def schedule(self) -> Dict[str, int]:
+        s = _lib.Schedule()
+        _check(lib.lbm_get_schedule(self._ctx, C.byref(s)), "lbm_get_schedule")
+        return {k: int(getattr(s, k)) for k, _ in _lib.Schedule._fields_}
+
+    @schedule.setter
+    def schedule(self, sched: Dict[str, int]):
+        cur = self.schedule
+        cur.update({k: int(v) for k, v in sched.items()})
+        s = _lib.Schedule(**cur)
+        _check(lib.lbm_set_schedule(self._ctx, C.byref(s)), f"lbm_set_schedule {cur}")
 
     def sync(self):
         _check(lib.lbm_sync(self._ctx), "lbm_sync")

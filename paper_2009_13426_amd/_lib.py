@@ -29,6 +29,11 @@ class Diag(C.Structure):
                 ("iter_hist", C.c_int64 * HIST_BINS), ("conserved", C.c_double * 4)]
 
 
+class Schedule(C.Structure):
+    _fields_ = [("step_block", C.c_int32), ("tiles_per_block", C.c_int32),
+                ("xcd_remap", C.c_int32), ("rebuild_blocks", C.c_int32)]
+
+
 # name -> (restype, argtypes); every function the header declares
 SIGNATURES = {
     "lbm_default_config": (None, [C.POINTER(Config), C.c_int32, C.c_int32]),
@@ -43,6 +48,10 @@ SIGNATURES = {
     "lbm_step_async": (C.c_int, [C.c_void_p, C.c_int32]),
     "lbm_step_profiled": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
+    "lbm_copy_state": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lbm_set_schedule": (C.c_int, [C.c_void_p, C.POINTER(Schedule)]),
+    "lbm_get_schedule": (C.c_int, [C.c_void_p, C.POINTER(Schedule)]),
+    "lbm_step_graph_async": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "lbm_sync": (C.c_int, [C.c_void_p]),
     "lbm_get_macros": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "lbm_get_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -40,6 +40,7 @@ struct DevDiag {
   unsigned long long newton_iters;
   unsigned long long mismatched;
   unsigned long long hist[LBM_HIST_BINS];
+  unsigned long long step_base;  // added to the step of a failure (graph replays)
 };
 
 enum : unsigned { kCodeNewton = 1, kCodeNonphysical = 2 };
@@ -76,6 +77,9 @@ struct StepArgs {
   GuessTable table;
   int step;
   DevDiag* diag;
+  int ntiles;  // tiles of BLOCK nodes
+  int tiles;   // tiles per workgroup, run one after the other
+  int remap;   // 1: workgroups mapped to tiles by XCD (xcd_remap)
 };
 
 struct RebuildArgs {
@@ -148,7 +152,7 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
 
 __device__ __forceinline__ void record_failure(DevDiag* d, int step, long long node,
                                                unsigned code) {
-  const unsigned long long key = (static_cast<unsigned long long>(step) << 34) |
+  const unsigned long long key = ((static_cast<unsigned long long>(step) + d->step_base) << 34) |
                                  (static_cast<unsigned long long>(node) << 3) | code;
   atomicMin(&d->fail_key, key);
 }
@@ -558,10 +562,22 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   }
 }
 
-template <typename S, bool STREAM, int BLOCK>
+// TILED: each workgroup runs a.tiles consecutive tiles in a loop (the loop
+// keeps kernel arguments live across the body, which costs spills); else
+// one tile per workgroup.
+template <typename S, bool STREAM, int BLOCK, bool TILED>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void step_kernel(StepArgs a) {
-  step_body<S, STREAM, BLOCK>(a, xcd_remap(blockIdx.x, gridDim.x));
+  const int g = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
+  if constexpr (TILED) {
+    for (int t = 0; t < a.tiles; ++t) {
+      const int b = g * a.tiles + t;
+      if (b >= a.ntiles) break;
+      step_body<S, STREAM, BLOCK>(a, b);
+    }
+  } else {
+    step_body<S, STREAM, BLOCK>(a, g);
+  }
 }
 
 // ------------------------------------------------------------ rebuild
@@ -702,6 +718,9 @@ __device__ __forceinline__ StepArgs job_step_args(const JobArgs& j, int s) {
   a.table = j.table;
   a.step = j.step0 + s + 1;
   a.diag = j.diag;
+  a.ntiles = j.nblocks;
+  a.tiles = 1;
+  a.remap = 0;
   return a;
 }
 
@@ -709,8 +728,8 @@ __device__ __forceinline__ StepArgs job_step_args(const JobArgs& j, int s) {
 // job by binary search over the jobs' first blocks.
 template <typename S, int BLOCK>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
-void step_batched_kernel(const JobArgs* jobs, int njobs, int s) {
-  const int gb = xcd_remap(blockIdx.x, gridDim.x);
+void step_batched_kernel(const JobArgs* jobs, int njobs, int s, int remap) {
+  const int gb = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -752,9 +771,10 @@ __global__ __launch_bounds__(kBlock) void rebuild_batched_kernel(const JobArgs* 
   }
 }
 
-// Lanes per workgroup of the step kernel: one wave.  The LDS parking area is
-// 42 x 64 values per wave (10.5 KB FP32, 21 KB FP64); single-wave blocks let
-// the LDS-bound FP64 form fit 7 waves per CU instead of 6.
+// Default lanes per workgroup of the step kernel: one wave.  The LDS parking
+// area is 42 x BLOCK values (10.5 KB FP32, 21 KB FP64 per wave); single-wave
+// blocks let the LDS-bound FP64 form fit 7 waves per CU instead of 6.  The
+// kernels are also built for 128 lanes, and for 256 in FP32 storage.
 template <typename S>
 constexpr int step_block() {
   return 64;

@@ -101,6 +101,29 @@ Layout layout(const lbm_config* c) {
 
 }  // namespace
 
+// A chunk of steps recorded as a HIP graph: kernel nodes only, for one
+// buffer parity (the chunk is even, so replays keep it).
+struct StepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int chunk = 0;
+  int cur = -1;     // buffer holding the state when a replay starts
+  int parity = -1;  // steps done mod 2 when a replay starts
+  std::vector<StepArgs> step_args;  // kernel arguments of the nodes
+  std::vector<RebuildArgs> rebuild_args;
+
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    chunk = 0;
+    cur = parity = -1;
+    step_args.clear();
+    rebuild_args.clear();
+  }
+};
+
 struct lbm_ctx {
   lbm_config cfg;
   Layout lay;
@@ -114,8 +137,15 @@ struct lbm_ctx {
   Phys phys;
   GuessTable table;
   int nblocks;       // 256-lane blocks (init, exports, reductions)
-  int step_blocks;   // blocks of the step kernel
-  int rebuild_blocks;  // blocks of the (grid-stride) rebuild kernel
+  lbm_schedule sched;  // step_block, tiles, remap, rebuild workgroups (resolved)
+  StepGraph graphs[2];  // by buffer parity
+
+  ~lbm_ctx() {
+    for (auto& g : graphs) g.reset();
+  }
+  int step_tiles() const {
+    return static_cast<int>((grid.N + sched.step_block - 1) / sched.step_block);
+  }
 
   void* f(int b) const { return ws + lay.off_pop[b]; }
   void* g(int b) const {
@@ -153,8 +183,65 @@ __global__ void diag_reset_kernel(DevDiag* d, unsigned* list_counters) {
   if (i < 2) list_counters[i] = 0u;
 }
 
-lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step) {
-  StepArgs a;
+// Device entry of the step kernel for a storage type, pass and block size;
+// nullptr for a combination that is not built.
+template <typename S, int B>
+const void* step_fn_of(bool tiled) {
+  return tiled ? reinterpret_cast<const void*>(&step_kernel<S, true, B, true>)
+               : reinterpret_cast<const void*>(&step_kernel<S, true, B, false>);
+}
+
+const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled) {
+  if (precision == LBM_FP64) {
+    if (!stream_pass)
+      return block == 64 && !tiled ? reinterpret_cast<const void*>(&step_kernel<double, false, 64, false>)
+                                   : nullptr;
+    switch (block) {
+      case 64: return step_fn_of<double, 64>(tiled);
+      case 128: return step_fn_of<double, 128>(tiled);
+    }
+  } else {
+    if (!stream_pass)
+      return block == 64 && !tiled ? reinterpret_cast<const void*>(&step_kernel<float, false, 64, false>)
+                                   : nullptr;
+    switch (block) {
+      case 64: return step_fn_of<float, 64>(tiled);
+      case 128: return step_fn_of<float, 128>(tiled);
+      case 256: return step_fn_of<float, 256>(tiled);
+    }
+  }
+  return nullptr;
+}
+
+const void* step_batched_fn(int precision, int block) {
+  if (precision == LBM_FP64) {
+    switch (block) {
+      case 64: return reinterpret_cast<const void*>(&step_batched_kernel<double, 64>);
+      case 128: return reinterpret_cast<const void*>(&step_batched_kernel<double, 128>);
+    }
+  } else {
+    switch (block) {
+      case 64: return reinterpret_cast<const void*>(&step_batched_kernel<float, 64>);
+      case 128: return reinterpret_cast<const void*>(&step_batched_kernel<float, 128>);
+      case 256: return reinterpret_cast<const void*>(&step_batched_kernel<float, 256>);
+    }
+  }
+  return nullptr;
+}
+
+// One launch of a single-argument kernel, as a direct launch or a graph node.
+template <typename Args>
+struct Launch {
+  const void* fn = nullptr;
+  dim3 grid, block;
+  Args args;
+};
+
+// The step from buffer src into dst; the collide-only pass of the initial
+// condition (stream_pass false) always runs one 64-lane tile per workgroup.
+Launch<StepArgs> step_launch(const lbm_ctx* c, int src, int dst, bool stream_pass, int step) {
+  Launch<StepArgs> L;
+  StepArgs& a = L.args;
   a.fin = c->f(src);
   a.gin = c->g(src);
   a.fout = c->f(dst);
@@ -167,28 +254,22 @@ lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step)
   a.table = c->table;
   a.step = step;
   a.diag = c->diag();
-  const dim3 grid(c->step_blocks);
-  if (c->cfg.precision == LBM_FP64) {
-    constexpr int B = step_block<double>();
-    if (stream_pass)
-      hipLaunchKernelGGL((step_kernel<double, true, B>), grid, dim3(B), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((step_kernel<double, false, B>), grid, dim3(B), 0, c->stream, a);
-  } else {
-    constexpr int B = step_block<float>();
-    if (stream_pass)
-      hipLaunchKernelGGL((step_kernel<float, true, B>), grid, dim3(B), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((step_kernel<float, false, B>), grid, dim3(B), 0, c->stream, a);
-  }
-  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+  const int B = stream_pass ? c->sched.step_block : 64;
+  a.ntiles = static_cast<int>((c->grid.N + B - 1) / B);
+  a.tiles = stream_pass ? c->sched.tiles_per_block : 1;
+  a.remap = stream_pass ? c->sched.xcd_remap : 1;
+  L.fn = step_kernel_fn(c->cfg.precision, stream_pass, B, a.tiles > 1);
+  L.grid = dim3(static_cast<unsigned>((a.ntiles + a.tiles - 1) / a.tiles));
+  L.block = dim3(B);
+  return L;
 }
 
 // Rebuilds the mismatched links of step `step` (pulling from buffer src)
-// into buffer dst.  Nothing to do with one lattice for all nodes.
-lbm_status launch_rebuild(lbm_ctx* c, int src, int dst, int step) {
-  if (c->cfg.shift_mode == LBM_SHIFT_FIXED) return LBM_OK;
-  RebuildArgs a;
+// into buffer dst.  No launch (fn nullptr) with one lattice for all nodes.
+Launch<RebuildArgs> rebuild_launch(const lbm_ctx* c, int src, int dst, int step) {
+  Launch<RebuildArgs> L;
+  if (c->cfg.shift_mode == LBM_SHIFT_FIXED) return L;
+  RebuildArgs& a = L.args;
   a.fout = c->f(dst);
   a.gout = c->g(dst);
   a.tags = c->tag(src);
@@ -198,12 +279,132 @@ lbm_status launch_rebuild(lbm_ctx* c, int src, int dst, int step) {
   a.table = c->table;
   a.step = step;
   a.diag = c->diag();
-  const dim3 grid(c->rebuild_blocks);
-  if (c->cfg.precision == LBM_FP64)
-    hipLaunchKernelGGL(rebuild_kernel<double>, grid, dim3(kBlock), 0, c->stream, a);
-  else
-    hipLaunchKernelGGL(rebuild_kernel<float>, grid, dim3(kBlock), 0, c->stream, a);
+  L.fn = c->cfg.precision == LBM_FP64 ? reinterpret_cast<const void*>(&rebuild_kernel<double>)
+                                      : reinterpret_cast<const void*>(&rebuild_kernel<float>);
+  L.grid = dim3(static_cast<unsigned>(c->sched.rebuild_blocks));
+  L.block = dim3(kBlock);
+  return L;
+}
+
+template <typename Args>
+lbm_status enqueue(const Launch<Args>& L, hipStream_t stream) {
+  if (!L.fn) return LBM_OK;
+  Args a = L.args;
+  void* params[] = {&a};
+  if (hipLaunchKernel(L.fn, L.grid, L.block, params, 0, stream) != hipSuccess) return LBM_ERR_HIP;
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step) {
+  const Launch<StepArgs> L = step_launch(c, src, dst, stream_pass, step);
+  if (!L.fn) return LBM_ERR_ARG;
+  return enqueue(L, c->stream);
+}
+
+lbm_status launch_rebuild(lbm_ctx* c, int src, int dst, int step) {
+  return enqueue(rebuild_launch(c, src, dst, step), c->stream);
+}
+
+__global__ void set_step_base_kernel(DevDiag* d, unsigned long long base) {
+  if (threadIdx.x == 0) d->step_base = base;
+}
+
+__global__ void advance_step_base_kernel(DevDiag* d, unsigned long long by) {
+  if (threadIdx.x == 0) d->step_base += by;
+}
+
+template <typename Args>
+lbm_status add_node(hipGraph_t g, hipGraphNode_t* prev, const Launch<Args>& L, Args* stored) {
+  hipKernelNodeParams p{};
+  void* params[] = {stored};
+  p.func = const_cast<void*>(L.fn);
+  p.gridDim = L.grid;
+  p.blockDim = L.block;
+  p.sharedMemBytes = 0;
+  p.kernelParams = params;
+  p.extra = nullptr;
+  hipGraphNode_t node = nullptr;
+  if (hipGraphAddKernelNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, &p) != hipSuccess)
+    return LBM_ERR_HIP;
+  *prev = node;
+  return LBM_OK;
+}
+
+// Records `chunk` steps starting from the context's current buffer and step
+// parity: per step the rebuild (if any) and the step, then the node that
+// advances the failure step base by the chunk.  Steps are recorded as
+// parity + 1 .. parity + chunk; a replay adds the base set before it.
+lbm_status build_graph(lbm_ctx* c, int chunk, StepGraph& G) {
+  G.reset();
+  const int parity = static_cast<int>(c->steps_done & 1);
+  G.step_args.reserve(chunk);
+  G.rebuild_args.reserve(chunk);
+  if (hipGraphCreate(&G.graph, 0) != hipSuccess) return LBM_ERR_HIP;
+  hipGraphNode_t prev = nullptr;
+  int cur = c->cur;
+  lbm_status st = LBM_OK;
+  for (int k = 1; k <= chunk && st == LBM_OK; ++k) {
+    const int src = cur, dst = 1 - cur;
+    const Launch<RebuildArgs> R = rebuild_launch(c, src, dst, parity + k);
+    if (R.fn) {
+      G.rebuild_args.push_back(R.args);
+      st = add_node(G.graph, &prev, R, &G.rebuild_args.back());
+    }
+    const Launch<StepArgs> S = step_launch(c, src, dst, true, parity + k);
+    if (st == LBM_OK && !S.fn) st = LBM_ERR_ARG;
+    if (st == LBM_OK) {
+      G.step_args.push_back(S.args);
+      st = add_node(G.graph, &prev, S, &G.step_args.back());
+    }
+    cur = dst;
+  }
+  if (st == LBM_OK) {
+    hipKernelNodeParams p{};
+    DevDiag* d = c->diag();
+    unsigned long long by = static_cast<unsigned long long>(chunk);
+    void* params[] = {&d, &by};
+    p.func = reinterpret_cast<void*>(&advance_step_base_kernel);
+    p.gridDim = dim3(1);
+    p.blockDim = dim3(64);
+    p.kernelParams = params;
+    hipGraphNode_t node = nullptr;
+    if (hipGraphAddKernelNode(&node, G.graph, &prev, 1, &p) != hipSuccess) st = LBM_ERR_HIP;
+  }
+  if (st == LBM_OK && hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0) != hipSuccess)
+    st = LBM_ERR_HIP;
+  if (st != LBM_OK) {
+    G.reset();
+    return st;
+  }
+  G.chunk = chunk;
+  G.cur = c->cur;
+  G.parity = parity;
+  return LBM_OK;
+}
+
+// Field by field (padding bytes of caller-built structs are not compared).
+bool same_config(const lbm_config& a, const lbm_config& b) {
+  return a.nx == b.nx && a.ny == b.ny && a.precision == b.precision && a.gamma == b.gamma &&
+         a.nu == b.nu && a.shift_mode == b.shift_mode && a.fixed_ux == b.fixed_ux &&
+         a.fixed_uy == b.fixed_uy && a.shift_halfwidth == b.shift_halfwidth &&
+         a.newton_tol == b.newton_tol && a.newton_max_iter == b.newton_max_iter &&
+         a.max_abs_shift == b.max_abs_shift && a.sensor == b.sensor &&
+         a.collect_stats == b.collect_stats;
+}
+
+// Default and checked schedules.
+int default_rebuild_blocks(long long N) {
+  return static_cast<int>(std::min<long long>((N + kBlock - 1) / kBlock, 4096));
+}
+
+bool schedule_ok(const lbm_ctx* c, const lbm_schedule* s) {
+  if (!s) return false;
+  if (!step_kernel_fn(c->cfg.precision, true, s->step_block, false)) return false;
+  if (!step_batched_fn(c->cfg.precision, s->step_block)) return false;
+  const long long tiles = (c->grid.N + s->step_block - 1) / s->step_block;
+  return s->tiles_per_block >= 1 && s->tiles_per_block <= 64 && tiles < (1ll << 31) &&
+         (s->xcd_remap == 0 || s->xcd_remap == 1) && s->rebuild_blocks >= 0 &&
+         s->rebuild_blocks <= 65535;
 }
 
 lbm_status read_status(lbm_ctx* c, unsigned long long* key_out) {
@@ -319,11 +520,10 @@ lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, s
   c->phys.sensor = cfg->sensor;
   c->phys.stats = cfg->collect_stats;
   c->nblocks = L.nparts;
-  {
-    const int B = cfg->precision == LBM_FP64 ? step_block<double>() : step_block<float>();
-    c->step_blocks = static_cast<int>((c->grid.N + B - 1) / B);
-    c->rebuild_blocks = static_cast<int>(std::min<long long>((c->grid.N + kBlock - 1) / kBlock, 4096));
-  }
+  c->sched.step_block = cfg->precision == LBM_FP64 ? step_block<double>() : step_block<float>();
+  c->sched.tiles_per_block = 1;
+  c->sched.xcd_remap = 1;
+  c->sched.rebuild_blocks = default_rebuild_blocks(c->grid.N);
   c->table.data = reinterpret_cast<const float*>(c->ws + L.table_off);
   c->table.nu = kTabU;
   c->table.ns = kTabS;
@@ -448,6 +648,57 @@ lbm_status lbm_step_profiled(lbm_ctx* c, int32_t nsteps, double* ms_rebuild, dou
   return read_status(c, nullptr);
 }
 
+lbm_status lbm_copy_state(lbm_ctx* dst, const lbm_ctx* src) {
+  if (!dst || !src || dst == src) return LBM_ERR_ARG;
+  if (!same_config(dst->cfg, src->cfg) || dst->device != src->device) return LBM_ERR_ARG;
+  if (!src->initialized) return LBM_ERR_STATE;
+  // every region before the table: buffers, tags, carried arrays, diagnostics
+  HIP_TRY(hipStreamSynchronize(src->stream));
+  HIP_TRY(hipMemcpyAsync(dst->ws, src->ws, src->lay.table_off, hipMemcpyDeviceToDevice,
+                         dst->stream));
+  HIP_TRY(hipStreamSynchronize(dst->stream));
+  dst->cur = src->cur;
+  dst->steps_done = src->steps_done;
+  dst->initialized = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_schedule(lbm_ctx* c, const lbm_schedule* sched) {
+  if (!c || !schedule_ok(c, sched)) return LBM_ERR_ARG;
+  c->sched = *sched;
+  if (c->sched.rebuild_blocks == 0) c->sched.rebuild_blocks = default_rebuild_blocks(c->grid.N);
+  for (auto& g : c->graphs) g.reset();
+  return LBM_OK;
+}
+
+lbm_status lbm_get_schedule(const lbm_ctx* c, lbm_schedule* sched) {
+  if (!c || !sched) return LBM_ERR_ARG;
+  *sched = c->sched;
+  return LBM_OK;
+}
+
+lbm_status lbm_step_graph_async(lbm_ctx* c, int32_t nsteps, int32_t chunk) {
+  if (!c || nsteps < 0 || chunk < 2 || chunk > 1024 || (chunk & 1)) return LBM_ERR_ARG;
+  if (!c->initialized) return LBM_ERR_STATE;
+  const int32_t reps = nsteps / chunk;
+  if (reps > 0) {
+    StepGraph& G = c->graphs[c->cur];
+    const int parity = static_cast<int>(c->steps_done & 1);
+    if (!G.exec || G.chunk != chunk || G.cur != c->cur || G.parity != parity) {
+      const lbm_status st = build_graph(c, chunk, G);
+      if (st) return st;
+    }
+    hipLaunchKernelGGL(set_step_base_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
+                       static_cast<unsigned long long>(c->steps_done - parity));
+    HIP_TRY(hipGetLastError());
+    for (int32_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(G.exec, c->stream));
+    hipLaunchKernelGGL(set_step_base_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(), 0ull);
+    HIP_TRY(hipGetLastError());
+    c->steps_done += static_cast<int64_t>(reps) * chunk;
+  }
+  return lbm_step_async(c, nsteps - reps * chunk);
+}
+
 lbm_status lbm_sync(lbm_ctx* c) {
   if (!c) return LBM_ERR_ARG;
   return read_status(c, nullptr);
@@ -564,6 +815,9 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
     nodes += c->grid.N;
   }
   // job table, blocks of the step launch in job order
+  const int B = ctxs[0]->sched.step_block;
+  const void* step_fn = step_batched_fn(ctxs[0]->cfg.precision, B);
+  if (!step_fn) return LBM_ERR_ARG;
   std::vector<JobArgs> jobs(n);
   long long blocks = 0;
   for (int32_t k = 0; k < n; ++k) {
@@ -582,8 +836,8 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
     j.step0 = static_cast<int>(c->steps_done);
     j.nsteps = nsteps[k];
     j.block0 = static_cast<int>(blocks);
-    j.nblocks = c->step_blocks;
-    blocks += c->step_blocks;
+    j.nblocks = static_cast<int>((c->grid.N + B - 1) / B);
+    blocks += j.nblocks;
   }
   if (blocks >= (1ll << 31)) return LBM_ERR_ARG;
   lbm_ctx* c0 = ctxs[0];
@@ -592,20 +846,17 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
                          c0->stream));
   const dim3 step_grid(static_cast<unsigned>(blocks));
   const dim3 rebuild_grid(static_cast<unsigned>(std::min<long long>((nodes + kBlock - 1) / kBlock, 4096)));
+  const void* rebuild_fn = c0->cfg.precision == LBM_FP64
+                              ? reinterpret_cast<const void*>(&rebuild_batched_kernel<double>)
+                              : reinterpret_cast<const void*>(&rebuild_batched_kernel<float>);
+  int remap = c0->sched.xcd_remap;
   for (int32_t st = 0; st < most; ++st) {
-    if (c0->cfg.precision == LBM_FP64) {
-      if (any_rebuild)
-        hipLaunchKernelGGL(rebuild_batched_kernel<double>, rebuild_grid, dim3(kBlock), 0,
-                           c0->stream, dev_jobs, n, st);
-      hipLaunchKernelGGL((step_batched_kernel<double, step_block<double>()>), step_grid,
-                         dim3(step_block<double>()), 0, c0->stream, dev_jobs, n, st);
-    } else {
-      if (any_rebuild)
-        hipLaunchKernelGGL(rebuild_batched_kernel<float>, rebuild_grid, dim3(kBlock), 0,
-                           c0->stream, dev_jobs, n, st);
-      hipLaunchKernelGGL((step_batched_kernel<float, step_block<float>()>), step_grid,
-                         dim3(step_block<float>()), 0, c0->stream, dev_jobs, n, st);
-    }
+    int njobs = n, s_arg = st;
+    void* rebuild_params[] = {&dev_jobs, &njobs, &s_arg};
+    void* step_params[] = {&dev_jobs, &njobs, &s_arg, &remap};
+    if (any_rebuild)
+      HIP_TRY(hipLaunchKernel(rebuild_fn, rebuild_grid, dim3(kBlock), rebuild_params, 0, c0->stream));
+    HIP_TRY(hipLaunchKernel(step_fn, step_grid, dim3(B), step_params, 0, c0->stream));
     HIP_TRY(hipGetLastError());
   }
   for (int32_t k = 0; k < n; ++k) {

@@ -158,9 +158,14 @@ def serve_one_at_a_time(requests: Sequence[Request], engine,
 class GpuEngine:
     """Jobs as `Sim` contexts on one device and one stream; batched steps
     through `lbm_step_batched`.  Every context copies the initial-guess table
-    of one template context instead of building its own."""
+    of one template context instead of building its own.
 
-    def __init__(self, precision: str = "fp32", device=None):
+    schedule "auto": the batched launches use the autotuner's batched-step
+    schedule and the one-job-at-a-time path each job's size-class schedule
+    (both from the cache; `prepare` tunes the missing ones before serving,
+    so that tuning never falls in served time).  None: library defaults."""
+
+    def __init__(self, precision: str = "fp32", device=None, schedule: Optional[str] = None):
         import torch
         from . import Sim, lib, make_config, workspace_bytes, _check
         self.torch = torch
@@ -170,6 +175,17 @@ class GpuEngine:
         self.device = torch.device("cuda" if device is None else device)
         self.stream = torch.cuda.current_stream(self.device)
         self.template = Sim(8, 8, device=self.device, stream=self.stream, precision=precision)
+        self.auto = schedule == "auto"
+        self.batch_schedule = None
+
+    def prepare(self, requests: Sequence[Request]):
+        """Tunes (or reads from the cache) every schedule the requests need."""
+        if not self.auto:
+            return
+        from . import autotune
+        self.batch_schedule = autotune.batched_schedule_for(self.precision, device=self.device)
+        for key in sorted({(r.nx, r.ny) for r in requests}):
+            autotune.schedule_for(self.precision, *key, device=self.device)
 
     def now(self) -> float:
         return time.perf_counter()
@@ -185,8 +201,11 @@ class GpuEngine:
         return self.workspace_bytes(cfg) + 4 * 8 * req.nx * req.ny
 
     def start(self, req: Request):
-        return self.Sim.from_workload(req.make(), precision=self.precision, device=self.device,
-                                      stream=self.stream, like=self.template)
+        sim = self.Sim.from_workload(req.make(), precision=self.precision, device=self.device,
+                                     stream=self.stream, like=self.template)
+        if self.batch_schedule:
+            sim.schedule = self.batch_schedule
+        return sim
 
     def run(self, sims, steps) -> List[int]:
         import ctypes as C
@@ -199,6 +218,11 @@ class GpuEngine:
         return [int(self.lib.lbm_sync(s.handle)) for s in sims]
 
     def run_alone(self, sim, steps: int) -> int:
+        if self.auto:
+            from . import autotune
+            sched = autotune.schedule_for(self.precision, sim.nx, sim.ny, tune_missing=False)
+            if sched:
+                sim.schedule = sched
         return int(self.lib.lbm_step(sim.handle, int(steps)))
 
     def release(self, sim):

@@ -35,12 +35,17 @@ def macros_of(sim):
     return {k: v.cpu().numpy() for k, v in m.items()}
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_mix_equals_alone(serve, precision):
+@pytest.mark.parametrize("precision,schedule", [("fp32", None), ("fp64", None), ("fp32", "auto")])
+def test_mix_equals_alone(serve, precision, schedule, tmp_path, monkeypatch):
     import paper_2009_13426_amd as lbm
+    from paper_2009_13426_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "schedules.json"))
     specs = small_mix()
     reqs = serve.requests_from_specs(specs, rate=150.0)
-    eng = serve.GpuEngine(precision=precision)
+    eng = serve.GpuEngine(precision=precision, schedule=schedule)
+    eng.prepare(reqs)
+    if schedule:
+        print("batched schedule", eng.batch_schedule, flush=True)
     got = {}
     rep = serve.serve(reqs, eng, memory_budget=1 << 34, quantum=10,
                       on_finish=lambda req, sim: got.__setitem__(req.job_id, macros_of(sim)))
