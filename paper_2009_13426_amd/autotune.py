@@ -29,6 +29,7 @@ STEP_BLOCKS = {"fp64": (64, 128), "fp32": (64, 128, 256)}
 TILES = (1, 2, 4)
 REMAPS = (1, 0)
 REBUILD_BLOCKS = (0, 256, 1024, 8192)
+MARGIN = 0.01   # relative gain a candidate needs over the best so far
 
 
 def default_cache_path() -> str:
@@ -100,21 +101,24 @@ def time_schedule(sim, sched: Dict[str, int], steps: int, repeats: int,
 def choose(sim, precision, steps: int = 8, repeats: int = 2,
            timer: Callable = time_schedule, reset: Optional[Callable] = None,
            step_cands: Optional[Iterable[dict]] = None,
-           rebuild_cands: Optional[Iterable[dict]] = None) -> dict:
+           rebuild_cands: Optional[Iterable[dict]] = None, margin: float = MARGIN) -> dict:
     """Times the candidates on `sim` and returns {"schedule": {...},
-    "step_ms": t, "rebuild_ms": t, "trials": [...]}."""
+    "step_ms": t, "rebuild_ms": t, "trials": [...]}.  A candidate replaces
+    the best so far only if faster by more than `margin` (relative), so
+    that timing noise does not move the choice away from the first
+    (default) candidate."""
     trials = []
     best, best_t = None, math.inf
     for cand in (step_cands if step_cands is not None else step_candidates(precision)):
         r, s = timer(sim, dict(cand, rebuild_blocks=0), steps, repeats, reset)
         trials.append(dict(cand, rebuild_blocks=0, step_ms=s, rebuild_ms=r))
-        if s < best_t:
+        if s < best_t * (1.0 - margin):
             best, best_t = dict(cand), s
     best_rb, best_rt = 0, math.inf
     for cand in (rebuild_cands if rebuild_cands is not None else rebuild_candidates()):
         r, s = timer(sim, dict(best, **cand), steps, repeats, reset)
         trials.append(dict(best, **cand, step_ms=s, rebuild_ms=r))
-        if r < best_rt:
+        if r < best_rt * (1.0 - margin):
             best_rb, best_rt = cand["rebuild_blocks"], r
     return dict(schedule=dict(best, rebuild_blocks=best_rb), step_ms=best_t, rebuild_ms=best_rt,
                 trials=trials)
@@ -203,7 +207,7 @@ def tune_batched(wls, precision="fp32", steps: int = 10, repeats: int = 2,
                 step_batched(sims, [steps] * n)
                 t = min(t, (time.perf_counter() - t0) * 1e3 / steps)
             trials.append(dict(cand, ms_per_step=t))
-            if t < best_t:
+            if t < best_t * (1.0 - MARGIN):
                 best, best_t = dict(cand), t
     finally:
         for s in sims:

@@ -69,11 +69,18 @@ __device__ __forceinline__ double exp_cw(double x) {
 #ifndef LBM_EXP_CW
 #define LBM_EXP_CW 1
 #endif
-// Reuse of the last factorisation for the final correction (1), or a fresh
-// factorisation (0, default: keeping the factors live costs registers).
-#ifndef LBM_NEWTON_REUSE_FACTORS
-#define LBM_NEWTON_REUSE_FACTORS 0
-#endif
+// Where a Newton solve may keep the LDL^T factors of its last step for the
+// final correction: 36 values per lane, element i at p[i * stride] (LDS),
+// rounded to FP32.  p == nullptr: no stash, the correction refactorises.
+struct FactorStash {
+  float* p;
+  int stride;
+};
+
+// A step whose largest exponent change is below this leaves the Hessian
+// close enough (relative change ~1e-6) for its factors to serve the next
+// iteration's correction.
+constexpr double kStashStep = 1e-5;
 __device__ __forceinline__ double exp_neg(double z) {
 #if LBM_EXP_CW
   return exp_cw(-z);
@@ -642,7 +649,8 @@ __device__ __forceinline__ void constraint_moments(const Weights& w, double (&c)
 // relative change is of the size of that step, so the correction is exact
 // to far below the tolerance.
 __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux, double uy,
-                                                double T, double tol, int max_iter, Weights& w) {
+                                                double T, double tol, int max_iter, Weights& w,
+                                                FactorStash stash = {nullptr, 0}) {
   NewtonOut out{0, false};
   {
     // The first weights must be of exponential form to full FP64 accuracy:
@@ -679,7 +687,7 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
                   : 2.0 * uy * ET;
   };
   double A[kTri];
-  bool reuse = false;  // A holds the factors of a Hessian close to the current one
+  bool stashed = false;  // the stash holds the factors of a Hessian close to the current one
   for (int it = 0; it < max_iter; ++it) {
     double G[kM];
     constraint_moments(w, G);
@@ -690,7 +698,12 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
     for (int a = 0; a < kM; ++a) r = fmax(r, fabs(G[a]));
     out.iters = it + 1;
     if (!(r < 1e300)) return out;
-    if (r <= tol && reuse) {
+    if (r <= tol && stashed) {
+      // final correction with the last step's factors: the residual is at
+      // the tolerance already, so FP32 factors of a Hessian that moved by
+      // ~1e-6 take it to round-off
+#pragma unroll
+      for (int i = 0; i < kTri; ++i) A[i] = static_cast<double>(stash.p[i * stash.stride]);
       ldl_solve_inplace(A, G);
       linear_update(G, w);
       out.ok = true;
@@ -719,8 +732,12 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
       for (int a = 0; a < kM; ++a) G[a] *= sc;
     }
     const double big = max_step_exponent(G, 0.0);
+    stashed = stash.p != nullptr && big < kStashStep;
+    if (stashed) {
+#pragma unroll
+      for (int i = 0; i < kTri; ++i) stash.p[i * stash.stride] = static_cast<float>(A[i]);
+    }
     exp_update(G, w, big);
-    reuse = LBM_NEWTON_REUSE_FACTORS && big < 1e-3;
   }
   return out;
 }
@@ -729,8 +746,9 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
 // from which plain Newton steps do not converge) the globalised solve_robust.
 __device__ __forceinline__ NewtonOut solve_equilibrium(const GuessTable& tb, double ux, double uy,
                                                        double T, double tol, int max_iter,
-                                                       Weights& w) {
-  NewtonOut out = solve_fast(tb, ux, uy, T, tol, max_iter, w);
+                                                       Weights& w,
+                                                       FactorStash stash = {nullptr, 0}) {
+  NewtonOut out = solve_fast(tb, ux, uy, T, tol, max_iter, w, stash);
   if (!out.ok) {
     double l[kM];
     const NewtonOut r = solve_robust(ux, uy, T, tol, max_iter, w, l);

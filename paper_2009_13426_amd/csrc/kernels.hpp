@@ -359,6 +359,10 @@ struct PullMap {
 template <typename S, bool STREAM, int BLOCK>
 __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   __shared__ S sh_pop[2 * kQ][BLOCK];
+  // FP32 storage: the Newton solve keeps its last factors here for the
+  // final correction (9 KB per wave; FP64's parking area leaves no room)
+  constexpr bool kStash = std::is_same<S, float>::value;
+  __shared__ float sh_fac[kStash ? kTri : 1][BLOCK];
   __shared__ unsigned long long sh_stat[2 + LBM_HIST_BINS];
 
   const int tid = threadIdx.x;
@@ -477,7 +481,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     }
     if (physical) {
       // a5: numerical equilibrium
-      const NewtonOut no = solve_equilibrium(a.table, upx, upy, T, P.tol, P.max_iter, w);
+      const NewtonOut no =
+          solve_equilibrium(a.table, upx, upy, T, P.tol, P.max_iter, w,
+                            FactorStash{kStash ? &sh_fac[0][tid] : nullptr, BLOCK});
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -678,7 +684,8 @@ __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
 }
 
 template <typename S>
-__global__ __launch_bounds__(kBlock) void rebuild_kernel(RebuildArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void rebuild_kernel(RebuildArgs a) {
   rebuild_body<S>(a);
 }
 
@@ -751,8 +758,8 @@ __global__ __launch_bounds__(kBlock) void gather_fail_keys_kernel(const JobArgs*
 // Rebuilds of step s for every job of a batch, each job's list spread over
 // the whole grid in turn.
 template <typename S>
-__global__ __launch_bounds__(kBlock) void rebuild_batched_kernel(const JobArgs* jobs, int njobs,
-                                                                 int s) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
   for (int k = 0; k < njobs; ++k) {
     const JobArgs& j = jobs[k];
     if (s >= j.nsteps || j.phys.shift_mode == 1) continue;

@@ -60,6 +60,16 @@ def test_choice_is_the_fastest_step_then_the_fastest_rebuild():
                for t in out["trials"][n_step:])
 
 
+def test_noise_below_the_margin_keeps_the_first_candidate():
+    def timer(sim, sched, steps, repeats, reset):
+        # the second candidate is 0.5 % faster: within the margin
+        return 0.2, 1.0 - (0.005 if sched["xcd_remap"] == 0 and sched["step_block"] == 64
+                           and sched["tiles_per_block"] == 1 else 0.0)
+    out = A.choose(FakeSim(), "fp64", timer=timer)
+    assert out["schedule"]["step_block"] == 64 and out["schedule"]["xcd_remap"] == 1
+    assert out["schedule"]["rebuild_blocks"] == 0
+
+
 def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "sub" / "schedules.json")
     assert A.load_cache(path) == {}

@@ -326,3 +326,69 @@ def smooth_random(nx: int, ny: int, seed: int, amp=(0.05, 0.2, 0.2, 0.05),
         out.append(_c(v))
     return Workload(f"smooth_{nx}x{ny}_{seed}", nx, ny, *out, nu, steps,
                     shift_mode, tuple(fixed_U))
+
+
+# ------------------------------------------------------------ linear regime
+# Sec. IV.B: small perturbations (A = 1e-3) of a uniform flow (rho0 = 1,
+# T0 = 0.7), inviscid (nu = 0, so tau = 1/2), periodic.  The mean velocities
+# are half-integers or integers; the hysteresis half-width 0.51 (the value
+# the paper's runs use) keeps round-off from flipping the lattice of a node
+# whose velocity sits on a half-integer.
+LINEAR_A = 1e-3
+LINEAR_HALFWIDTH = 0.51
+
+
+def linear_steps(u0: float, L: int = 100, periods: int = 15) -> int:
+    """Steps of `periods` flow-through times t_c = L / u0 (Sec. IV.B.1: an
+    integer for u0 in {2, 2.5, 3} at L = 100)."""
+    t = periods * L / u0
+    if abs(t - round(t)) > 1e-9:
+        raise ValueError(f"{periods} t_c is not a whole number of steps at u0 = {u0}")
+    return int(round(t))
+
+
+def shear_wave(u0: float, nx: int = 100, steps: int | None = None) -> Workload:
+    """Sec. IV.B.1: u_y = A sin(2 pi x / L_x) on a uniform flow u_x = u0,
+    nx x 1 nodes; compared after 15 t_c."""
+    x, _ = _grid(nx, 1)
+    f = lambda v: np.full((1, nx), v, dtype=np.float64)
+    steps = linear_steps(u0, nx) if steps is None else steps
+    return Workload(f"shear_wave_u{u0:g}", nx, 1, f(RHO0), f(u0),
+                    _c(LINEAR_A * np.sin(2 * math.pi * x / nx)), f(T0), 0.0, steps,
+                    halfwidth=LINEAR_HALFWIDTH, meta=dict(u0=u0, A=LINEAR_A))
+
+
+def _spot(L: int):
+    x, y = _grid(L, L)
+    R = L / 10.0
+    return np.exp(-((x - L / 2) ** 2 + (y - L / 2) ** 2) / R ** 2)
+
+
+def entropy_spot(u0: float, L: int = 100, steps: int | None = None) -> Workload:
+    """Sec. IV.B.2: Gaussian hot spot at constant pressure, rho = rho0 (1 -
+    A e^{-r^2}), T = T0 (1 + A e^{-r^2}), r^2 = |x - x_c|^2 / R^2, R = L/10,
+    centre (L/2, L/2), on u_x = u0; compared after 15 t_c."""
+    g = _spot(L)
+    f = lambda v: np.full((L, L), v, dtype=np.float64)
+    steps = linear_steps(u0, L) if steps is None else steps
+    return Workload(f"entropy_spot_u{u0:g}", L, L, _c(RHO0 * (1 - LINEAR_A * g)), f(u0), f(0.0),
+                    _c(T0 * (1 + LINEAR_A * g)), 0.0, steps, halfwidth=LINEAR_HALFWIDTH,
+                    meta=dict(u0=u0, A=LINEAR_A))
+
+
+ACOUSTIC_STEPS = 30
+
+
+def acoustic_pulse(u0: float, L: int = 100, steps: int = ACOUSTIC_STEPS) -> Workload:
+    """Sec. IV.B.3: Gaussian pressure pulse P = P0 (1 + A e^{-r^2}) on u_x =
+    u0, isentropic: rho = rho0 (P/P0)^{1/gamma}, T = T0 (rho/rho0)^{gamma-1}
+    (so that P = rho T); 30 steps.  u0 in {0, 1.3, 2.6, 3.9} (the figure's
+    values) moves the pulse by a whole number of nodes in 30 steps."""
+    g = _spot(L)
+    P0 = RHO0 * T0
+    P = P0 * (1 + LINEAR_A * g)
+    rho = RHO0 * (P / P0) ** (1.0 / GAMMA)
+    T = T0 * (rho / RHO0) ** (GAMMA - 1.0)
+    f = lambda v: np.full((L, L), v, dtype=np.float64)
+    return Workload(f"acoustic_pulse_u{u0:g}", L, L, _c(rho), f(u0), f(0.0), _c(T), 0.0, steps,
+                    halfwidth=LINEAR_HALFWIDTH, meta=dict(u0=u0, A=LINEAR_A))
