@@ -84,13 +84,13 @@ def profile_figures():
     return out
 
 
-def time_form(lbm, torch, wl, precision, steps, warmup, schedule=None, chunk=10):
+def time_form(lbm, torch, wl, precision, steps, warmup, schedule=None, chunk=10, **over):
     """Timed region: `steps` steps between two synchronisations, run as
     replays of a HIP graph of `chunk` steps (lbm_step_graph_async; the graph
     is built during the warm-up).  A second pass of `steps` steps with HIP
     events around every launch on the library's stream gives the step and
     link-rebuild kernels' own durations."""
-    sim = lbm.Sim.from_workload(wl, precision=precision, schedule=schedule)
+    sim = lbm.Sim.from_workload(wl, precision=precision, schedule=schedule, **over)
     sched = sim.schedule
     graphed = warmup - warmup % chunk
     if graphed:
@@ -188,6 +188,8 @@ def main():
                     help="launch schedule: the autotuner's choice for the grid's size class "
                          "(cached; tuned before the timed region on a miss) or the library "
                          "default")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip timing the four-constraint equilibrium variant (FP32 storage)")
     ap.add_argument("--graph-chunk", type=int, default=10,
                     help="steps per HIP graph replayed in the timed region (even)")
     ap.add_argument("--forms", default="fp32,fp64")
@@ -232,6 +234,17 @@ def main():
         print(f"[bench] {form}: {res[form]['mlups']:.1f} MLUPS, step kernel "
               f"{res[form]['kernel_ms']:.3f} ms, rebuild kernel {res[form]['rebuild_ms']:.3f} ms",
               file=sys.stderr, flush=True)
+    variants = {}
+    if not args.no_variants:
+        print("[bench] timing the four-constraint variant (fp32)", file=sys.stderr, flush=True)
+        v = time_form(lbm, torch, wl, "fp32", args.steps, args.warmup, None, args.graph_chunk,
+                      constraints=4)
+        variants["fp32_constraints4"] = dict(
+            mlups=round(v["mlups"], 2), kernel_ms=round(v["kernel_ms"], 4),
+            rebuild_ms=round(v["rebuild_ms"], 4), status=v["status"],
+            equilibrium="mass, momentum and energy constraints only (4 x 4 solve)")
+        print(f"[bench] fp32 four constraints: {v['mlups']:.1f} MLUPS", file=sys.stderr,
+              flush=True)
     head = "fp32" if "fp32" in res else next(iter(res))
     counters = {f: {} for f in res}
     if not args.no_counters:
@@ -279,7 +292,7 @@ def main():
                              f"shifts, Knudsen sensor, nu={wl.nu:g}, seeded draw",
                     nodes=nodes, precision=head, schedule=res[head]["schedule"],
                     graph_chunk=args.graph_chunk),
-        roofline=roofline, cpu_baseline=cpu, serving=serving,
+        roofline=roofline, cpu_baseline=cpu, serving=serving, variants=variants or None,
         forms={f: dict(mlups=round(r["mlups"], 2), kernel_ms=round(r["kernel_ms"], 4),
                        rebuild_ms=round(r["rebuild_ms"], 4), schedule=r["schedule"],
                        hbm_gbs=round(bytes_per_node(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9, 1),

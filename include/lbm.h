@@ -79,6 +79,10 @@ typedef struct {
   int32_t max_abs_shift;     /* admissible |U_alpha|, 0..12 */
   int32_t sensor;            /* 1: tau scaled by alpha(eps_Kn), eq. (DeltaAvg) */
   int32_t collect_stats;     /* 1: keep Newton/mismatch counters (small cost) */
+  int32_t constraints;       /* moment constraints of the numerical equilibrium:
+                                8 = eq. (8moments) (default); 4 = mass, momentum and
+                                energy only, eq. (feqNum_4Mom), Sec. "Reduced models"
+                                (4 x 4 solve; runs the default schedule only) */
 } lbm_config;
 
 typedef struct {
@@ -109,7 +113,7 @@ typedef struct {
 
 /* Fills cfg with the defaults used by the paper's tests: gamma 1.4, nu 0,
  * adaptive shifts with half-width 0.5, Newton tolerance 1e-12 and 30
- * iterations, |U| <= 6, FP64, no sensor, no counters. */
+ * iterations, |U| <= 6, FP64, no sensor, no counters, 8 constraints. */
 void lbm_default_config(lbm_config* cfg, int32_t nx, int32_t ny);
 
 /* Device bytes the context needs for cfg (two population buffers, lattice
@@ -126,7 +130,8 @@ lbm_status lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes,
 
 /* As lbm_create, but the initial-guess table is copied (device to device, on
  * the stream) from the existing context `like` on the same device instead of
- * being built (for callers that create many contexts, e.g. a job server).
+ * being built (for callers that create many contexts, e.g. a job server);
+ * built as by lbm_create if `like` has another constraint count.
  * `like` stays valid and unchanged; the copy is ordered on hip_stream. */
 lbm_status lbm_create_like(const lbm_ctx* like, const lbm_config* cfg, void* dev_workspace,
                            size_t bytes, void* hip_stream, lbm_ctx** out);
@@ -210,8 +215,8 @@ void lbm_velocities(int32_t* cx, int32_t* cy);
  * fixed summation order).  out: host pointer.  Synchronous. */
 lbm_status lbm_get_diag(lbm_ctx* ctx, lbm_diag* out);
 
-/* Advances n <= 1024 distinct contexts that share one HIP stream, device and
- * precision: ctxs[k] by nsteps[k] steps.  Per step one rebuild launch and
+/* Advances n <= 1024 distinct contexts that share one HIP stream, device,
+ * precision and constraint count: ctxs[k] by nsteps[k] steps.  Per step one rebuild launch and
  * one step launch cover all contexts still running (the job table lives in
  * ctxs[0]'s workspace).  The step launch takes step_block and xcd_remap
  * from ctxs[0]'s schedule and runs one tile per workgroup; the rebuild

@@ -27,7 +27,7 @@ class Params(C.Structure):
                 ("nu", C.c_double), ("shift_mode", C.c_int), ("fixed_ux", C.c_int),
                 ("fixed_uy", C.c_int), ("halfwidth", C.c_double),
                 ("newton_tol", C.c_double), ("newton_max_iter", C.c_int),
-                ("max_abs_shift", C.c_int), ("sensor", C.c_int)]
+                ("max_abs_shift", C.c_int), ("sensor", C.c_int), ("constraints", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -53,6 +53,10 @@ def lib():
                                       C.c_double, C.c_int, dp, dp, ip]
         L.orc_equilibrium.restype = C.c_int
         L.orc_targets.argtypes = [C.c_double, C.c_double, C.c_double, dp]
+        L.orc_equilibrium_m.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp,
+                                        C.c_double, C.c_int, dp, dp, ip]
+        L.orc_equilibrium_m.restype = C.c_int
+        L.orc_targets_m.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, dp]
         L.orc_grad_populations.argtypes = [C.POINTER(Params), C.c_double, C.c_double,
                                            C.c_double, C.c_double, dp, dp, C.c_int,
                                            C.c_int, C.c_int, dp, dp]
@@ -97,18 +101,25 @@ def targets(ux, uy, T):
     return m
 
 
-def equilibrium(ux, uy, T, lam0=None, tol=1e-12, max_iter=100):
-    """Weights w (per unit density), multipliers, iterations, status."""
+def equilibrium(ux, uy, T, lam0=None, tol=1e-12, max_iter=100, constraints=M):
+    """Weights w (per unit density), multipliers, iterations, status.
+    constraints: 8 (eq. 8moments) or 4 (mass, momentum, energy)."""
     w = np.zeros(Q)
-    lam = np.zeros(M)
+    lam = np.zeros(constraints)
     it = C.c_int(0)
     l0 = None
     if lam0 is not None:
         l0 = np.ascontiguousarray(lam0, dtype=np.float64)
-    rc = lib().orc_equilibrium(float(ux), float(uy), float(T),
-                               _dp(l0) if l0 is not None else None, tol, max_iter,
-                               _dp(w), _dp(lam), C.byref(it))
+    rc = lib().orc_equilibrium_m(int(constraints), float(ux), float(uy), float(T),
+                                 _dp(l0) if l0 is not None else None, tol, max_iter,
+                                 _dp(w), _dp(lam), C.byref(it))
     return w, lam, it.value, rc
+
+
+def targets_m(constraints, ux, uy, T):
+    m = np.zeros(constraints)
+    lib().orc_targets_m(int(constraints), ux, uy, T, _dp(m))
+    return m
 
 
 def select(u, Uprev, halfwidth=0.5):
@@ -117,9 +128,9 @@ def select(u, Uprev, halfwidth=0.5):
 
 def make_params(nx, ny, gamma=1.4, nu=1e-3, shift_mode=0, fixed_U=(0, 0),
                 halfwidth=0.5, newton_tol=1e-12, newton_max_iter=100,
-                max_abs_shift=6, sensor=0) -> Params:
+                max_abs_shift=6, sensor=0, constraints=8) -> Params:
     return Params(nx, ny, gamma, nu, shift_mode, fixed_U[0], fixed_U[1], halfwidth,
-                  newton_tol, newton_max_iter, max_abs_shift, sensor)
+                  newton_tol, newton_max_iter, max_abs_shift, sensor, constraints)
 
 
 def grad_populations(params: Params, rho, ux, uy, T, du, dT, L, post):

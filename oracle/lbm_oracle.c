@@ -50,7 +50,7 @@ void orc_velocities(int* cx, int* cy) {
  * with the integer-valued xi_i and the peculiar velocity u - U; the span of
  * phi is invariant under integer translations, so this is the same
  * equilibrium as the one written with c_i = xi_i + U and u. */
-static void basis(int i, double phi[ORC_M]) {
+static void basis8(int i, double phi[ORC_M]) {
   double x = XI[i][0], y = XI[i][1];
   double s = x * x + y * y;
   phi[0] = 1.0;
@@ -63,10 +63,34 @@ static void basis(int i, double phi[ORC_M]) {
   phi[7] = y * s;
 }
 
+/* Sec. "Reduced models", eq. (feqNum_4Mom): the four constraints of mass,
+ * momentum and total energy, phi = (1, xi_x, xi_y, |xi|^2). */
+static void basis4(int i, double phi[ORC_M]) {
+  double x = XI[i][0], y = XI[i][1];
+  phi[0] = 1.0;
+  phi[1] = x;
+  phi[2] = y;
+  phi[3] = x * x + y * y;
+}
+
+static void basis(int M, int i, double phi[ORC_M]) {
+  if (M == 4)
+    basis4(i, phi);
+  else
+    basis8(i, phi);
+}
+
 /* Constraint targets per unit density, eqs. (G0_8mom)-(G3yaa_8mom), with the
  * energy 2E = u_x^2 + u_y^2 + D T (App. C, D = 2). */
-void orc_targets(double ux, double uy, double T, double* m) {
+void orc_targets_m(int M, double ux, double uy, double T, double* m) {
   double E = 0.5 * (ux * ux + uy * uy + ORC_D * T);
+  if (M == 4) { /* G_0, G_1x, G_1y, G_2aa of the four-constraint set */
+    m[0] = 1.0;
+    m[1] = ux;
+    m[2] = uy;
+    m[3] = 2.0 * E;
+    return;
+  }
   m[0] = 1.0;
   m[1] = ux;
   m[2] = uy;
@@ -77,65 +101,67 @@ void orc_targets(double ux, double uy, double T, double* m) {
   m[7] = 2.0 * uy * (E + T);
 }
 
+void orc_targets(double ux, double uy, double T, double* m) { orc_targets_m(8, ux, uy, T, m); }
+
 /* Weights w_i = exp(-(1 + lambda.phi_i)), constraint residuals
  * G_a = sum_i w_i phi_a(xi_i) - m_a (eq. constraints) and the value of the
  * convex dual Psi(lambda) = sum_i w_i + lambda.m, whose gradient is -G and
  * whose Hessian is H = sum_i w_i phi phi^T (positive definite since phi has
  * rank 8 on the lattice).  Minimising Psi is the entropy problem of
  * eqs. (Hfunction)-(exponential) with prefactor a = rho. */
-static double evaluate(const double lam[ORC_M], const double m[ORC_M],
+static double evaluate(int M, const double lam[ORC_M], const double m[ORC_M],
                        double w[ORC_Q], double G[ORC_M]) {
   double phi[ORC_M];
   double psi = 0.0;
-  for (int a = 0; a < ORC_M; ++a) G[a] = -m[a];
+  for (int a = 0; a < M; ++a) G[a] = -m[a];
   for (int i = 0; i < ORC_Q; ++i) {
-    basis(i, phi);
+    basis(M, i, phi);
     double e = 1.0;
-    for (int a = 0; a < ORC_M; ++a) e += lam[a] * phi[a];
+    for (int a = 0; a < M; ++a) e += lam[a] * phi[a];
     w[i] = exp(-e);
-    for (int a = 0; a < ORC_M; ++a) G[a] += w[i] * phi[a];
+    for (int a = 0; a < M; ++a) G[a] += w[i] * phi[a];
     psi += w[i];
   }
-  for (int a = 0; a < ORC_M; ++a) psi += lam[a] * m[a];
+  for (int a = 0; a < M; ++a) psi += lam[a] * m[a];
   return psi;
 }
 
-static void hessian(const double w[ORC_Q], double H[ORC_M][ORC_M]) {
+static void hessian(int M, const double w[ORC_Q], double H[ORC_M][ORC_M]) {
   double phi[ORC_M];
   memset(H, 0, sizeof(double) * ORC_M * ORC_M);
   for (int i = 0; i < ORC_Q; ++i) {
-    basis(i, phi);
-    for (int a = 0; a < ORC_M; ++a)
-      for (int b = 0; b < ORC_M; ++b) H[a][b] += w[i] * phi[a] * phi[b];
+    basis(M, i, phi);
+    for (int a = 0; a < M; ++a)
+      for (int b = 0; b < M; ++b) H[a][b] += w[i] * phi[a] * phi[b];
   }
 }
 
-/* Gaussian elimination with partial pivoting for H d = G. */
-static int solve(double Hin[ORC_M][ORC_M], const double G[ORC_M], double d[ORC_M]) {
+/* Gaussian elimination with partial pivoting for H d = G (leading M x M). */
+static int solve(int M, double Hin[ORC_M][ORC_M], const double G[ORC_M], double d[ORC_M]) {
   double A[ORC_M][ORC_M + 1];
-  for (int r = 0; r < ORC_M; ++r) {
-    for (int c = 0; c < ORC_M; ++c) A[r][c] = Hin[r][c];
-    A[r][ORC_M] = G[r];
+  for (int r = 0; r < M; ++r) {
+    for (int c = 0; c < M; ++c) A[r][c] = Hin[r][c];
+    A[r][M] = G[r];
   }
-  for (int c = 0; c < ORC_M; ++c) {
+  for (int c = 0; c < M; ++c) {
     int p = c;
-    for (int r = c + 1; r < ORC_M; ++r)
+    for (int r = c + 1; r < M; ++r)
       if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
     if (!(fabs(A[p][c]) > 0.0)) return -1;
     if (p != c)
-      for (int k = 0; k <= ORC_M; ++k) {
+      for (int k = 0; k <= M; ++k) {
         double t = A[c][k];
         A[c][k] = A[p][k];
         A[p][k] = t;
       }
-    for (int r = c + 1; r < ORC_M; ++r) {
+    for (int r = c + 1; r < M; ++r) {
       double f = A[r][c] / A[c][c];
-      for (int k = c; k <= ORC_M; ++k) A[r][k] -= f * A[c][k];
+      for (int k = c; k <= M; ++k) A[r][k] -= f * A[c][k];
     }
   }
-  for (int r = ORC_M - 1; r >= 0; --r) {
-    double acc = A[r][ORC_M];
-    for (int k = r + 1; k < ORC_M; ++k) acc -= A[r][k] * d[k];
+  for (int r = M - 1; r >= 0; --r) {
+    double acc = A[r][M];
+    for (int k = r + 1; k < M; ++k) acc -= A[r][k] * d[k];
     d[r] = acc / A[r][r];
   }
   return 0;
@@ -151,20 +177,20 @@ static double maxabs(const double* v, int n) {
 }
 
 /* Initial guess: the lattice-normalised Maxwellian, lambda_1 = -u/T,
- * lambda_2 = I / (2T), cross and third-order multipliers zero, lambda_0
- * such that sum_i w_i = 1. */
-static void maxwellian_guess(double ux, double uy, double T, double lam[ORC_M]) {
+ * lambda_2 = I / (2T) (for M = 4 the |xi|^2 multiplier 1/(2T)), cross and
+ * third-order multipliers zero, lambda_0 such that sum_i w_i = 1. */
+static void maxwellian_guess(int M, double ux, double uy, double T, double lam[ORC_M]) {
   double phi[ORC_M];
   for (int a = 0; a < ORC_M; ++a) lam[a] = 0.0;
   lam[1] = -ux / T;
   lam[2] = -uy / T;
   lam[3] = 0.5 / T;
-  lam[5] = 0.5 / T;
+  if (M == 8) lam[5] = 0.5 / T;
   double z = 0.0;
   for (int i = 0; i < ORC_Q; ++i) {
-    basis(i, phi);
+    basis(M, i, phi);
     double e = 0.0;
-    for (int a = 1; a < ORC_M; ++a) e += lam[a] * phi[a];
+    for (int a = 1; a < M; ++a) e += lam[a] * phi[a];
     z += exp(-e);
   }
   lam[0] = log(z) - 1.0;
@@ -177,41 +203,43 @@ static void maxwellian_guess(double ux, double uy, double T, double lam[ORC_M]) 
  * falls below its rounding).  Stop when max_a |G_a| <= tol, then apply one
  * more plain Newton step so that the constraints hold to rounding.
  * Reading: the polishing step. */
-int orc_equilibrium(double ux, double uy, double T, const double* lam0,
-                    double tol, int max_iter, double* w, double* lam, int* iters) {
+int orc_equilibrium_m(int M, double ux, double uy, double T, const double* lam0,
+                      double tol, int max_iter, double* w, double* lam, int* iters) {
   double m[ORC_M], l[ORC_M], G[ORC_M], d[ORC_M], H[ORC_M][ORC_M];
   double wt[ORC_Q], lt[ORC_M], Gt[ORC_M];
   if (iters) *iters = 0;
+  if (M != 4 && M != 8) return ORC_ERR_ARG;
   if (!(T > 0.0) || !isfinite(T) || !isfinite(ux) || !isfinite(uy))
     return ORC_ERR_NONPHYSICAL;
-  orc_targets(ux, uy, T, m);
+  orc_targets_m(M, ux, uy, T, m);
+  for (int a = 0; a < ORC_M; ++a) l[a] = 0.0;
   if (lam0)
-    memcpy(l, lam0, sizeof l);
+    memcpy(l, lam0, sizeof(double) * M);
   else
-    maxwellian_guess(ux, uy, T, l);
-  double psi = evaluate(l, m, w, G);
+    maxwellian_guess(M, ux, uy, T, l);
+  double psi = evaluate(M, l, m, w, G);
   for (int it = 0; it < max_iter; ++it) {
-    double r = maxabs(G, ORC_M);
+    double r = maxabs(G, M);
     if (!isfinite(r) || !isfinite(psi)) return ORC_ERR_NEWTON;
-    hessian(w, H);
-    if (solve(H, G, d)) return ORC_ERR_NEWTON;
+    hessian(M, w, H);
+    if (solve(M, H, G, d)) return ORC_ERR_NEWTON;
     if (r <= tol) { /* converged: one polishing Newton step */
-      for (int a = 0; a < ORC_M; ++a) l[a] += d[a];
-      evaluate(l, m, w, G);
-      if (!isfinite(maxabs(G, ORC_M))) return ORC_ERR_NEWTON;
-      memcpy(lam, l, sizeof l);
+      for (int a = 0; a < M; ++a) l[a] += d[a];
+      evaluate(M, l, m, w, G);
+      if (!isfinite(maxabs(G, M))) return ORC_ERR_NEWTON;
+      memcpy(lam, l, sizeof(double) * M);
       if (iters) *iters = it + 1;
       return ORC_OK;
     }
     double slope = 0.0; /* directional derivative of Psi along d: -G.d < 0 */
-    for (int a = 0; a < ORC_M; ++a) slope -= G[a] * d[a];
+    for (int a = 0; a < M; ++a) slope -= G[a] * d[a];
     double t = 1.0, psit;
     for (;;) {
-      for (int a = 0; a < ORC_M; ++a) lt[a] = l[a] + t * d[a];
-      psit = evaluate(lt, m, wt, Gt);
+      for (int a = 0; a < M; ++a) lt[a] = l[a] + t * d[a];
+      psit = evaluate(M, lt, m, wt, Gt);
       if (isfinite(psit)) {
         if (psit <= psi + 1e-4 * t * slope) break;
-        if (t == 1.0 && maxabs(Gt, ORC_M) < 0.5 * r) break;
+        if (t == 1.0 && maxabs(Gt, M) < 0.5 * r) break;
       }
       t *= 0.5;
       if (t < 1e-12) return ORC_ERR_NEWTON;
@@ -223,6 +251,14 @@ int orc_equilibrium(double ux, double uy, double T, const double* lam0,
   }
   return ORC_ERR_NEWTON;
 }
+
+int orc_equilibrium(double ux, double uy, double T, const double* lam0,
+                    double tol, int max_iter, double* w, double* lam, int* iters) {
+  return orc_equilibrium_m(8, ux, uy, T, lam0, tol, max_iter, w, lam, iters);
+}
+
+/* Constraint count of a simulation: 8 (eq. 8moments) unless set to 4. */
+static int constraints_of(const orc_params* p) { return p->constraints == 4 ? 4 : 8; }
 
 /* ------------------------------------------------------ Grad populations
  * Eqs. (GradGeneral), (GradGeneral_f), (GradGeneral_g):
@@ -264,8 +300,8 @@ int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
   double w[ORC_Q], lam[ORC_M];
   double Cv = 1.0 / (p->gamma - 1.0);
   if (!(rho > 0.0) || !isfinite(rho)) return ORC_ERR_NONPHYSICAL;
-  int rc = orc_equilibrium(ux - Lx, uy - Ly, T, NULL, p->newton_tol,
-                           p->newton_max_iter, w, lam, NULL);
+  int rc = orc_equilibrium_m(constraints_of(p), ux - Lx, uy - Ly, T, NULL, p->newton_tol,
+                             p->newton_max_iter, w, lam, NULL);
   if (rc) return rc;
   double tau = 0.5 + p->nu / T;
   double k = post ? (1.0 - 1.0 / tau) : 1.0;
@@ -311,7 +347,8 @@ int orc_select(double u, int Uprev, double halfwidth) {
 
 orc_sim* orc_create(const orc_params* p) {
   if (!p || p->nx < 1 || p->ny < 1 || !(p->gamma > 1.0) || !(p->nu >= 0.0) ||
-      p->newton_max_iter < 1 || !(p->halfwidth >= 0.5))
+      p->newton_max_iter < 1 || !(p->halfwidth >= 0.5) ||
+      (p->constraints != 0 && p->constraints != 4 && p->constraints != 8))
     return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   if (!s) return NULL;
@@ -429,8 +466,8 @@ static int collide_all(orc_sim* s) {
     /* numerical equilibrium in the current lattice, eqs. (feqNum_8Mom), (gEq) */
     double w[ORC_Q], lam[ORC_M];
     int it = 0;
-    int rc = orc_equilibrium(upx, upy, T, NULL, p->newton_tol, p->newton_max_iter, w,
-                             lam, &it);
+    int rc = orc_equilibrium_m(constraints_of(p), upx, upy, T, NULL, p->newton_tol,
+                               p->newton_max_iter, w, lam, &it);
     calls += 1;
     iters += it;
     if (rc) {

@@ -47,6 +47,8 @@ typedef struct {
   int newton_max_iter;
   int max_abs_shift;     /* |U_alpha| above this is reported as non-physical */
   int sensor;            /* 1: Knudsen sensor scales tau by alpha(eps_Kn) */
+  int constraints;       /* 8 (or 0): eq. (8moments); 4: mass, momentum and energy
+                            only, eq. (feqNum_4Mom) */
 } orc_params;
 
 typedef struct {
@@ -73,6 +75,13 @@ int orc_equilibrium(double ux, double uy, double T, const double* lam0,
 
 /* Exact targets m[8] of the 8 constraints per unit density. */
 void orc_targets(double ux, double uy, double T, double* m);
+
+/* As orc_equilibrium / orc_targets for M = 8 or M = 4 constraints (M = 4:
+ * phi = (1, xi_x, xi_y, |xi|^2), targets (1, u_x, u_y, 2E)); lam and m hold
+ * M values.  ORC_ERR_ARG for another M. */
+int orc_equilibrium_m(int M, double ux, double uy, double T, const double* lam0,
+                      double tol, int max_iter, double* w, double* lam, int* iters);
+void orc_targets_m(int M, double ux, double uy, double T, double* m);
 
 /* Grad populations h = h_eq (1 + phi) for lattice shift (Lx, Ly) at a state
  * with gradients du = (dux/dx, dux/dy, duy/dx, duy/dy), dT = (dT/dx, dT/dy).

@@ -45,7 +45,7 @@ def velocities():
 
 def make_config(nx: int, ny: int, precision="fp64", gamma=1.4, nu=0.0, shift_mode="adaptive",
                 fixed_U=(0, 0), halfwidth=0.5, newton_tol=1e-12, newton_max_iter=30,
-                max_abs_shift=6, sensor=False, stats=False) -> _lib.Config:
+                max_abs_shift=6, sensor=False, stats=False, constraints=8) -> _lib.Config:
     cfg = _lib.Config()
     lib.lbm_default_config(C.byref(cfg), int(nx), int(ny))
     cfg.precision = PRECISIONS[precision]
@@ -59,6 +59,7 @@ def make_config(nx: int, ny: int, precision="fp64", gamma=1.4, nu=0.0, shift_mod
     cfg.max_abs_shift = int(max_abs_shift)
     cfg.sensor = int(bool(sensor))
     cfg.collect_stats = int(bool(stats))
+    cfg.constraints = int(constraints)
     return cfg
 
 

@@ -19,6 +19,7 @@
 #include <type_traits>
 
 #include "equilibrium.hpp"
+#include "equilibrium4.hpp"
 #include "lattice.hpp"
 
 #ifndef LBM_HIST_BINS
@@ -111,13 +112,6 @@ struct InitArgs {
 };
 
 // ------------------------------------------------------------ helpers
-template <int K, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (K < N) {
-    f(std::integral_constant<int, K>{});
-    static_for<K + 1, N>(f);
-  }
-}
 
 __device__ __forceinline__ int wrapc(int v, int n, int fast) {
   if (fast) {
@@ -261,11 +255,24 @@ __device__ __forceinline__ void carried_uT(const S* mac, const int* tags, long l
   T = static_cast<double>(mac[3 * N + s]);
 }
 
+// The numerical equilibrium of the context's constraint set: the 8-moment
+// set (eq. feqNum_8Mom, default) or mass, momentum and energy only (M = 4,
+// eq. feqNum_4Mom).
+template <int M>
+__device__ __forceinline__ NewtonOut solve_of(const GuessTable& tb, double ux, double uy,
+                                              double T, const Phys& P, Weights& w,
+                                              FactorStash stash = {nullptr, 0}) {
+  if constexpr (M == 4)
+    return solve_equilibrium4(tb, ux, uy, T, P.tol, P.max_iter, w);
+  else
+    return solve_equilibrium(tb, ux, uy, T, P.tol, P.max_iter, w, stash);
+}
+
 // Post-collision population of velocity plane k in the receiver's lattice
 // (Lx, Ly), rebuilt at source node s by Grad's ansatz from the moments of
 // s's last collision and central differences of its neighbours' (eq.
 // GradGeneral with h* = h_eq + (1 - 1/tau) h_neq, tau = 1/2 + nu / T(s)).
-template <typename S>
+template <typename S, int M>
 __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long s, int Lx, int Ly,
                                               int k, double& rf, double& rg, int& iters) {
   const CarryT<S>* mac = static_cast<const CarryT<S>*>(a.carry.mac);
@@ -299,7 +306,7 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
     dT[1] = 0.5 * (Sp - Sm);
   }
   Weights w;
-  const NewtonOut no = solve_equilibrium(a.table, ux - Lx, uy - Ly, T, P.tol, P.max_iter, w);
+  const NewtonOut no = solve_of<M>(a.table, ux - Lx, uy - Ly, T, P, w);
   iters = no.iters;
   if (!no.ok) return kCodeNewton;
   double wk = 0.0, cxk = 0.0, cyk = 0.0;
@@ -356,12 +363,12 @@ struct PullMap {
 // the node's own slot of the output buffer and are read from there.  The
 // tail prepares the next step: moments of this collision, the mask of the
 // next pull's rebuilt links, and the list of nodes that have any.
-template <typename S, bool STREAM, int BLOCK>
+template <typename S, bool STREAM, int BLOCK, int M>
 __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   __shared__ S sh_pop[2 * kQ][BLOCK];
   // FP32 storage: the Newton solve keeps its last factors here for the
   // final correction (9 KB per wave; FP64's parking area leaves no room)
-  constexpr bool kStash = std::is_same<S, float>::value;
+  constexpr bool kStash = std::is_same<S, float>::value && M == 8;
   __shared__ float sh_fac[kStash ? kTri : 1][BLOCK];
   __shared__ unsigned long long sh_stat[2 + LBM_HIST_BINS];
 
@@ -482,8 +489,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     if (physical) {
       // a5: numerical equilibrium
       const NewtonOut no =
-          solve_equilibrium(a.table, upx, upy, T, P.tol, P.max_iter, w,
-                            FactorStash{kStash ? &sh_fac[0][tid] : nullptr, BLOCK});
+          solve_of<M>(a.table, upx, upy, T, P, w,
+                      FactorStash{kStash ? &sh_fac[0][tid] : nullptr, BLOCK});
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -571,7 +578,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
 // TILED: each workgroup runs a.tiles consecutive tiles in a loop (the loop
 // keeps kernel arguments live across the body, which costs spills); else
 // one tile per workgroup.
-template <typename S, bool STREAM, int BLOCK, bool TILED>
+template <typename S, bool STREAM, int BLOCK, bool TILED, int M = kM>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void step_kernel(StepArgs a) {
   const int g = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -579,10 +586,10 @@ void step_kernel(StepArgs a) {
     for (int t = 0; t < a.tiles; ++t) {
       const int b = g * a.tiles + t;
       if (b >= a.ntiles) break;
-      step_body<S, STREAM, BLOCK>(a, b);
+      step_body<S, STREAM, BLOCK, M>(a, b);
     }
   } else {
-    step_body<S, STREAM, BLOCK>(a, g);
+    step_body<S, STREAM, BLOCK, M>(a, g);
   }
 }
 
@@ -593,7 +600,7 @@ void step_kernel(StepArgs a) {
 // receivers' links into (receiver, link) items and hands them out one per
 // lane.  Grid-stride over the list; clears the other list counter for the
 // coming step's appends.
-template <typename S>
+template <typename S, int M>
 __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
   __shared__ int sh_node[kWaves][64];
   __shared__ int sh_k[kWaves][64];
@@ -665,7 +672,7 @@ __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
                             wrapc(xx - (cx + Lx), nx, a.grid.fast_x);
         double rf, rg;
         int it;
-        const unsigned code = rebuild_link<S>(a, s, Lx, Ly, k, rf, rg, it);
+        const unsigned code = rebuild_link<S, M>(a, s, Lx, Ly, k, rf, rg, it);
         if (code) record_failure(a.diag, a.step, s, code);
         plane_at(fout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rf);
         plane_at(gout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rg);
@@ -683,10 +690,10 @@ __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
   }
 }
 
-template <typename S>
+template <typename S, int M = kM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void rebuild_kernel(RebuildArgs a) {
-  rebuild_body<S>(a);
+  rebuild_body<S, M>(a);
 }
 
 // ------------------------------------------------------------ batched
@@ -733,7 +740,7 @@ __device__ __forceinline__ StepArgs job_step_args(const JobArgs& j, int s) {
 
 // Step s of a batch: the grid covers every job's blocks; a block finds its
 // job by binary search over the jobs' first blocks.
-template <typename S, int BLOCK>
+template <typename S, int BLOCK, int M = kM>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void step_batched_kernel(const JobArgs* jobs, int njobs, int s, int remap) {
   const int gb = remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -745,7 +752,7 @@ void step_batched_kernel(const JobArgs* jobs, int njobs, int s, int remap) {
   }
   const JobArgs& j = jobs[lo];
   if (s >= j.nsteps || gb - j.block0 >= j.nblocks) return;
-  step_body<S, true, BLOCK>(job_step_args<S>(j, s), gb - j.block0);
+  step_body<S, true, BLOCK, M>(job_step_args<S>(j, s), gb - j.block0);
 }
 
 // Failure words of every job of a batch, gathered for one copy to the host.
@@ -757,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void gather_fail_keys_kernel(const JobArgs*
 
 // Rebuilds of step s for every job of a batch, each job's list spread over
 // the whole grid in turn.
-template <typename S>
+template <typename S, int M = kM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
   for (int k = 0; k < njobs; ++k) {
@@ -774,7 +781,7 @@ void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
     a.table = j.table;
     a.step = j.step0 + s + 1;
     a.diag = j.diag;
-    rebuild_body<S>(a);
+    rebuild_body<S, M>(a);
   }
 }
 
@@ -817,10 +824,39 @@ __global__ __launch_bounds__(256) void table_kernel(float* out, int nu, int ns, 
   o[7] = 1.0f;
 }
 
+// The guess table of the four-constraint set: the same grid and records,
+// first four floats l1x + a s, l1y + b s, l2 - s / 2, 1 (NaN where the
+// globalised solve did not converge), the rest zero.
+__global__ __launch_bounds__(256) void table4_kernel(float* out, int nu, int ns, float umax,
+                                                     float smin, float smax, double tol,
+                                                     int max_iter) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nu * nu * ns) return;
+  const int ia = idx % nu, ib = (idx / nu) % nu, is = idx / (nu * nu);
+  const double a = umax * static_cast<double>(ia) / (nu - 1);
+  const double b = umax * static_cast<double>(ib) / (nu - 1);
+  const double s = smin + (smax - smin) * static_cast<double>(is) / (ns - 1);
+  const double T = 1.0 / s;
+  double m[kM4], l[kM4];
+  targets4(a, b, T, m);
+  Weights w;
+  const NewtonOut no = solve_robust4(m, T, tol, max_iter, w, l);
+  float* o = out + 8l * idx;
+  for (int k = 0; k < 8; ++k) o[k] = 0.0f;
+  if (!no.ok) {
+    o[3] = __builtin_nanf("");
+    return;
+  }
+  o[0] = static_cast<float>(l[1] + a * s);
+  o[1] = static_cast<float>(l[2] + b * s);
+  o[2] = static_cast<float>(l[3] - 0.5 * s);
+  o[3] = 1.0f;
+}
+
 // ------------------------------------------------------------ init
 // Grad initial condition: lattice from u (or fixed / static), equilibrium
 // there, central differences of the input fields, h(0) = h_eq (1 + phi).
-template <typename S>
+template <typename S, int M = kM>
 __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a) {
   const long long n = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   const long long N = a.grid.N;
@@ -850,7 +886,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a) {
   a.tout[n] = tag_pack(Ux, Uy, Ux, Uy);
   Weights w;
   if (!code) {
-    const NewtonOut no = solve_equilibrium(a.table, ux - Ux, uy - Uy, T, P.tol, P.max_iter, w);
+    const NewtonOut no = solve_of<M>(a.table, ux - Ux, uy - Uy, T, P, w);
     if (!no.ok) code = kCodeNewton;
   }
   if (code) {

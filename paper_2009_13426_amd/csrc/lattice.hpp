@@ -8,8 +8,19 @@
 #pragma once
 
 #include <cstdint>
+#include <type_traits>
 
 namespace lbm {
+
+// f(integral_constant<int, K>) ... f(integral_constant<int, N - 1>), unrolled
+// at compile time (velocity components become constants).
+template <int K, int N, typename F>
+__host__ __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (K < N) {
+    f(std::integral_constant<int, K>{});
+    static_for<K + 1, N>(f);
+  }
+}
 
 constexpr int kQ = 21;
 constexpr int kPairs = 10;

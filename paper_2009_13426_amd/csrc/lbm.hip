@@ -56,7 +56,8 @@ bool config_ok(const lbm_config* c) {
          c->shift_mode >= 0 && c->shift_mode <= 2 && c->shift_halfwidth >= 0.5 &&
          c->shift_halfwidth < 8.0 && c->newton_tol > 0.0 && c->newton_max_iter >= 1 &&
          c->newton_max_iter <= 1000 && c->max_abs_shift >= 0 && c->max_abs_shift <= 12 &&
-         std::abs(c->fixed_ux) <= c->max_abs_shift && std::abs(c->fixed_uy) <= c->max_abs_shift;
+         std::abs(c->fixed_ux) <= c->max_abs_shift && std::abs(c->fixed_uy) <= c->max_abs_shift &&
+         (c->constraints == kM || c->constraints == 4);
 }
 
 Layout layout(const lbm_config* c) {
@@ -191,8 +192,21 @@ const void* step_fn_of(bool tiled) {
                : reinterpret_cast<const void*>(&step_kernel<S, true, B, false>);
 }
 
-const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled) {
-  if (precision == LBM_FP64) {
+// Device entry of the step kernel for a storage type, pass, block size,
+// tiling and constraint count; nullptr for a combination that is not built
+// (the four-constraint set is built for 64-lane untiled blocks only).
+const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled, int M) {
+  const bool f64 = precision == LBM_FP64;
+  if (M == 4) {
+    if (block != 64 || tiled) return nullptr;
+    if (f64)
+      return stream_pass ? reinterpret_cast<const void*>(&step_kernel<double, true, 64, false, 4>)
+                         : reinterpret_cast<const void*>(&step_kernel<double, false, 64, false, 4>);
+    return stream_pass ? reinterpret_cast<const void*>(&step_kernel<float, true, 64, false, 4>)
+                       : reinterpret_cast<const void*>(&step_kernel<float, false, 64, false, 4>);
+  }
+  if (M != kM) return nullptr;
+  if (f64) {
     if (!stream_pass)
       return block == 64 && !tiled ? reinterpret_cast<const void*>(&step_kernel<double, false, 64, false>)
                                    : nullptr;
@@ -213,8 +227,15 @@ const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tile
   return nullptr;
 }
 
-const void* step_batched_fn(int precision, int block) {
-  if (precision == LBM_FP64) {
+const void* step_batched_fn(int precision, int block, int M) {
+  const bool f64 = precision == LBM_FP64;
+  if (M == 4) {
+    if (block != 64) return nullptr;
+    return f64 ? reinterpret_cast<const void*>(&step_batched_kernel<double, 64, 4>)
+               : reinterpret_cast<const void*>(&step_batched_kernel<float, 64, 4>);
+  }
+  if (M != kM) return nullptr;
+  if (f64) {
     switch (block) {
       case 64: return reinterpret_cast<const void*>(&step_batched_kernel<double, 64>);
       case 128: return reinterpret_cast<const void*>(&step_batched_kernel<double, 128>);
@@ -227,6 +248,24 @@ const void* step_batched_fn(int precision, int block) {
     }
   }
   return nullptr;
+}
+
+const void* rebuild_fn(int precision, int M) {
+  const bool f64 = precision == LBM_FP64;
+  if (M == 4)
+    return f64 ? reinterpret_cast<const void*>(&rebuild_kernel<double, 4>)
+               : reinterpret_cast<const void*>(&rebuild_kernel<float, 4>);
+  return f64 ? reinterpret_cast<const void*>(&rebuild_kernel<double>)
+             : reinterpret_cast<const void*>(&rebuild_kernel<float>);
+}
+
+const void* rebuild_batched_fn(int precision, int M) {
+  const bool f64 = precision == LBM_FP64;
+  if (M == 4)
+    return f64 ? reinterpret_cast<const void*>(&rebuild_batched_kernel<double, 4>)
+               : reinterpret_cast<const void*>(&rebuild_batched_kernel<float, 4>);
+  return f64 ? reinterpret_cast<const void*>(&rebuild_batched_kernel<double>)
+             : reinterpret_cast<const void*>(&rebuild_batched_kernel<float>);
 }
 
 // One launch of a single-argument kernel, as a direct launch or a graph node.
@@ -258,7 +297,7 @@ Launch<StepArgs> step_launch(const lbm_ctx* c, int src, int dst, bool stream_pas
   a.ntiles = static_cast<int>((c->grid.N + B - 1) / B);
   a.tiles = stream_pass ? c->sched.tiles_per_block : 1;
   a.remap = stream_pass ? c->sched.xcd_remap : 1;
-  L.fn = step_kernel_fn(c->cfg.precision, stream_pass, B, a.tiles > 1);
+  L.fn = step_kernel_fn(c->cfg.precision, stream_pass, B, a.tiles > 1, c->cfg.constraints);
   L.grid = dim3(static_cast<unsigned>((a.ntiles + a.tiles - 1) / a.tiles));
   L.block = dim3(B);
   return L;
@@ -279,8 +318,7 @@ Launch<RebuildArgs> rebuild_launch(const lbm_ctx* c, int src, int dst, int step)
   a.table = c->table;
   a.step = step;
   a.diag = c->diag();
-  L.fn = c->cfg.precision == LBM_FP64 ? reinterpret_cast<const void*>(&rebuild_kernel<double>)
-                                      : reinterpret_cast<const void*>(&rebuild_kernel<float>);
+  L.fn = rebuild_fn(c->cfg.precision, c->cfg.constraints);
   L.grid = dim3(static_cast<unsigned>(c->sched.rebuild_blocks));
   L.block = dim3(kBlock);
   return L;
@@ -389,7 +427,7 @@ bool same_config(const lbm_config& a, const lbm_config& b) {
          a.fixed_uy == b.fixed_uy && a.shift_halfwidth == b.shift_halfwidth &&
          a.newton_tol == b.newton_tol && a.newton_max_iter == b.newton_max_iter &&
          a.max_abs_shift == b.max_abs_shift && a.sensor == b.sensor &&
-         a.collect_stats == b.collect_stats;
+         a.collect_stats == b.collect_stats && a.constraints == b.constraints;
 }
 
 // Default and checked schedules.
@@ -399,8 +437,10 @@ int default_rebuild_blocks(long long N) {
 
 bool schedule_ok(const lbm_ctx* c, const lbm_schedule* s) {
   if (!s) return false;
-  if (!step_kernel_fn(c->cfg.precision, true, s->step_block, false)) return false;
-  if (!step_batched_fn(c->cfg.precision, s->step_block)) return false;
+  const bool tiled = s->tiles_per_block > 1;
+  if (!step_kernel_fn(c->cfg.precision, true, s->step_block, tiled, c->cfg.constraints))
+    return false;
+  if (!step_batched_fn(c->cfg.precision, s->step_block, c->cfg.constraints)) return false;
   const long long tiles = (c->grid.N + s->step_block - 1) / s->step_block;
   return s->tiles_per_block >= 1 && s->tiles_per_block <= 64 && tiles < (1ll << 31) &&
          (s->xcd_remap == 0 || s->xcd_remap == 1) && s->rebuild_blocks >= 0 &&
@@ -437,10 +477,16 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
   a.phys = c->phys;
   a.table = c->table;
   a.diag = c->diag();
-  if (c->cfg.precision == LBM_FP64)
+  if (c->cfg.constraints == 4) {
+    if (c->cfg.precision == LBM_FP64)
+      hipLaunchKernelGGL((init_kernel<double, 4>), dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((init_kernel<float, 4>), dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
+  } else if (c->cfg.precision == LBM_FP64) {
     hipLaunchKernelGGL(init_kernel<double>, dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
-  else
+  } else {
     hipLaunchKernelGGL(init_kernel<float>, dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
+  }
   HIP_TRY(hipGetLastError());
   lbm_status st = launch_step(c, 0, 1, false, 0);
   if (st) return st;
@@ -470,6 +516,7 @@ void lbm_default_config(lbm_config* c, int32_t nx, int32_t ny) {
   c->max_abs_shift = 6;
   c->sensor = 0;
   c->collect_stats = 0;
+  c->constraints = kM;
 }
 
 size_t lbm_workspace_bytes(const lbm_config* cfg) {
@@ -535,17 +582,22 @@ lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, s
   hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
                      c->carry().counters);
   const size_t table_bytes = static_cast<size_t>(kTabU) * kTabU * kTabS * 8 * sizeof(float);
-  if (like) {
+  if (like && like->cfg.constraints == cfg->constraints) {
     if (hipMemcpyAsync(c->ws + L.table_off, like->ws + like->lay.table_off, table_bytes,
                        hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
       delete c;
       return LBM_ERR_HIP;
     }
   } else {
+    // the table of the context's constraint set, built on the device
     const int pts = kTabU * kTabU * kTabS;
-    hipLaunchKernelGGL(table_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream,
-                       reinterpret_cast<float*>(c->ws + L.table_off), kTabU, kTabS, kTabUmax,
-                       kTabSmin, kTabSmax, 1e-13, 100);
+    float* tab = reinterpret_cast<float*>(c->ws + L.table_off);
+    if (cfg->constraints == 4)
+      hipLaunchKernelGGL(table4_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream, tab,
+                         kTabU, kTabS, kTabUmax, kTabSmin, kTabSmax, 1e-13, 100);
+    else
+      hipLaunchKernelGGL(table_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream, tab,
+                         kTabU, kTabS, kTabUmax, kTabSmin, kTabSmax, 1e-13, 100);
   }
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
     delete c;
@@ -804,7 +856,8 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
   for (int32_t k = 0; k < n; ++k) {
     lbm_ctx* c = ctxs[k];
     if (!c || nsteps[k] < 0) return LBM_ERR_ARG;
-    if (c->cfg.precision != ctxs[0]->cfg.precision || c->stream != ctxs[0]->stream ||
+    if (c->cfg.precision != ctxs[0]->cfg.precision ||
+        c->cfg.constraints != ctxs[0]->cfg.constraints || c->stream != ctxs[0]->stream ||
         c->device != ctxs[0]->device)
       return LBM_ERR_ARG;
     for (int32_t m = 0; m < k; ++m)
@@ -816,7 +869,7 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
   }
   // job table, blocks of the step launch in job order
   const int B = ctxs[0]->sched.step_block;
-  const void* step_fn = step_batched_fn(ctxs[0]->cfg.precision, B);
+  const void* step_fn = step_batched_fn(ctxs[0]->cfg.precision, B, ctxs[0]->cfg.constraints);
   if (!step_fn) return LBM_ERR_ARG;
   std::vector<JobArgs> jobs(n);
   long long blocks = 0;
@@ -846,16 +899,15 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
                          c0->stream));
   const dim3 step_grid(static_cast<unsigned>(blocks));
   const dim3 rebuild_grid(static_cast<unsigned>(std::min<long long>((nodes + kBlock - 1) / kBlock, 4096)));
-  const void* rebuild_fn = c0->cfg.precision == LBM_FP64
-                              ? reinterpret_cast<const void*>(&rebuild_batched_kernel<double>)
-                              : reinterpret_cast<const void*>(&rebuild_batched_kernel<float>);
+  const void* rebuild_batched = rebuild_batched_fn(c0->cfg.precision, c0->cfg.constraints);
   int remap = c0->sched.xcd_remap;
   for (int32_t st = 0; st < most; ++st) {
     int njobs = n, s_arg = st;
     void* rebuild_params[] = {&dev_jobs, &njobs, &s_arg};
     void* step_params[] = {&dev_jobs, &njobs, &s_arg, &remap};
     if (any_rebuild)
-      HIP_TRY(hipLaunchKernel(rebuild_fn, rebuild_grid, dim3(kBlock), rebuild_params, 0, c0->stream));
+      HIP_TRY(hipLaunchKernel(rebuild_batched, rebuild_grid, dim3(kBlock), rebuild_params, 0,
+                              c0->stream));
     HIP_TRY(hipLaunchKernel(step_fn, step_grid, dim3(B), step_params, 0, c0->stream));
     HIP_TRY(hipGetLastError());
   }

@@ -1,0 +1,138 @@
+"""Pins of the oracle's four-constraint equilibrium (Sec. "Reduced models",
+eq. feqNum_4Mom: mass, momentum and total energy only) to what the paper
+and the mathematics fix.  The basis and targets below are written from the
+paper's four constraints G_0, G_1x, G_1y, G_2aa, independently of
+oracle/lbm_oracle.c."""
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize
+
+import workloads as W
+
+EPS = np.finfo(float).eps
+
+
+def basis4(c):
+    x, y = c[:, 0].astype(float), c[:, 1].astype(float)
+    return np.stack([np.ones_like(x), x, y, x * x + y * y], 1)
+
+
+def targets4(ux, uy, T, D=2):
+    """sum f = rho, sum f xi = rho u, sum f |xi|^2 = 2 rho E, 2E = |u|^2 + D T."""
+    return np.array([1.0, ux, uy, ux * ux + uy * uy + D * T])
+
+
+STATES = [(0.0, 0.0, 0.7), (0.3, -0.2, 0.7), (0.5, 0.5, 0.5), (-0.45, 0.1, 1.4),
+          (1.0, 0.0, 0.7), (0.7, -0.6, 1.0)]
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES)
+def test_four_constraints_reproduced(orc, ux, uy, T):
+    w, lam, it, rc = orc.equilibrium(ux, uy, T, constraints=4)
+    assert rc == 0 and lam.shape == (4,)
+    c = orc.velocities()
+    P = basis4(c)
+    m = targets4(ux, uy, T)
+    assert np.max(np.abs(P.T @ w - m) / np.maximum(np.abs(m), 1.0)) < 1e-13
+    # exponential form with exactly these multipliers
+    assert np.max(np.abs(w - np.exp(-(1.0 + P @ lam))) / w) < 1e-12
+    assert np.array_equal(orc.targets_m(4, ux, uy, T), targets4(ux, uy, T))
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES[1:])
+def test_four_constraint_root_against_powell_hybrid(orc, ux, uy, T):
+    """The same problem solved by MINPACK's hybrid Powell method from a
+    different start gives the same weights (the dual is strictly convex, so
+    the root is unique)."""
+    P = basis4(orc.velocities())
+    m = targets4(ux, uy, T)
+
+    def G(lam):
+        return P.T @ np.exp(-(1 + P @ lam)) - m
+
+    def J(lam):
+        w = np.exp(-(1 + P @ lam))
+        return -(P * w[:, None]).T @ P
+
+    # a Maxwellian-like start written independently of the oracle's
+    lam0 = np.array([0.0, -ux / T, -uy / T, 0.5 / T])
+    lam0[0] = math.log(np.exp(-(P[:, 1:] @ lam0[1:])).sum()) - 1
+    sol = scipy.optimize.root(G, lam0, jac=J, method="hybr", options=dict(xtol=1e-15))
+    assert np.max(np.abs(G(sol.x))) < 1e-12
+    w, lam, it, rc = orc.equilibrium(ux, uy, T, constraints=4)
+    assert rc == 0
+    assert np.max(np.abs(w - np.exp(-(1 + P @ sol.x))) / w) < 1e-10
+
+
+@pytest.mark.parametrize("T", [0.5, 0.7, 1.4])
+def test_rest_state_equals_the_eight_constraint_equilibrium(orc, T):
+    """At u' = 0 both constraint sets reduce to w_i ~ exp(-beta |xi_i|^2)
+    (symmetry and uniqueness), so the two equilibria coincide."""
+    w4, _, _, rc4 = orc.equilibrium(0.0, 0.0, T, constraints=4)
+    w8, _, _, rc8 = orc.equilibrium(0.0, 0.0, T)
+    assert rc4 == 0 and rc8 == 0
+    assert np.max(np.abs(w4 - w8) / w8) < 1e-12
+
+
+def test_pressure_tensor_is_left_free_at_nonzero_velocity(orc):
+    """Only the trace of the pressure tensor is constrained: at u' = (0.3, 0)
+    the four-constraint equilibrium misses P_xx - P_yy = u_x^2 by a finite
+    amount (the convective error the paper attributes to this set), while
+    the eight-constraint one matches it to rounding; at u' = 0 both match."""
+    c = orc.velocities().astype(float)
+    x, y = c[:, 0], c[:, 1]
+    ux, T = 0.3, 0.7
+    w4, *_ = orc.equilibrium(ux, 0.0, T, constraints=4)
+    w8, *_ = orc.equilibrium(ux, 0.0, T)
+    dev4 = (w4 * (x * x - y * y)).sum() - ux * ux
+    dev8 = (w8 * (x * x - y * y)).sum() - ux * ux
+    assert abs(dev8) < 1e-13
+    assert abs(dev4) > 1e-4
+    assert abs((w4 * (x * x + y * y)).sum() - (ux * ux + 2 * T)) < 1e-13
+    w0, *_ = orc.equilibrium(0.0, 0.0, T, constraints=4)
+    assert abs((w0 * (x * x - y * y)).sum()) < 1e-14
+
+
+def test_conservation_without_interfaces_four_constraints(orc):
+    """The four constraints are exactly the collision invariants, so with
+    one fixed lattice the sums of mass, momentum and energy drift only by
+    rounding (eqs. coll, gEq, polyTemp)."""
+    wl = W.smooth_random(24, 20, seed=3, amp=(0.1, 0.3, 0.3, 0.1),
+                         base=(1.0, 1.2, -0.3, 0.8), shift_mode=1, fixed_U=(1, 0), nu=5e-3)
+    s = orc.Sim.from_workload(wl, constraints=4)
+    c0 = s.conserved()
+    s.step(20)
+    c1 = s.conserved()
+    scale = np.array([c0[0], c0[0] * 3, c0[0] * 3, c0[3]])
+    assert np.all(np.abs(c1 - c0) <= 64 * EPS * 20 * scale), (c1 - c0) / scale
+
+
+def test_uniform_state_stays_uniform_four_constraints(orc):
+    wl = W.uniform(8, 6, 1.0, 1.3, -0.4, 0.8, shift_mode=0)
+    s = orc.Sim.from_workload(wl, constraints=4)
+    m0 = s.macros()
+    s.step(10)
+    m1 = s.macros()
+    for k in ("rho", "ux", "uy", "T"):
+        assert np.max(np.abs(m1[k] - m0[k])) < 1e-14, k
+
+
+def test_invalid_constraint_counts_are_rejected(orc):
+    w, lam, it, rc = orc.equilibrium(0.1, 0.0, 0.7, constraints=5)
+    assert rc == orc.ERR_ARG
+    with pytest.raises(ValueError):
+        orc.Sim(4, 4, constraints=6)
+
+
+def test_sets_differ_away_from_rest(orc):
+    """The sets agree at rest and their weights move apart as the relative
+    velocity grows (the four-constraint set leaves the pressure tensor and
+    the heat flux free)."""
+    d = []
+    for ux in (0.1, 0.2, 0.4):
+        w4, *_ = orc.equilibrium(ux, 0.0, 0.7, constraints=4)
+        w8, *_ = orc.equilibrium(ux, 0.0, 0.7)
+        d.append(np.max(np.abs(w4 - w8)))
+    assert 1e-6 < d[0] < d[1] < d[2]
