@@ -258,3 +258,29 @@ def test_failures_are_reported(orc):
         s2 = orc.Sim(4, 4, shift_mode=0, max_abs_shift=6)
         s2.init(*wl.fields())
     assert e.value.rc == orc.ERR_NONPHYSICAL
+
+
+def test_printed_heat_flux_terms_carry_a_fraction_of_q(orc):
+    """Reading D-6 as printed: the heat-flux moment (1/2) sum xi (|xi|^2 f + g)
+    of a Grad state with q = -rho Cp nu grad T.  The g term 2 q.c/(rho Cp)
+    contributes exactly (2 Cv - 2) T^2 / Cp q (it uses only the enforced
+    moment sum xi_x^2 f_eq = rho T), i.e. 0.42 q at T = 0.7 instead of the
+    internal-energy share; the f term adds about -0.27 q on this lattice, so
+    the state carries ~0.15 q in total.  The same term forms make up the
+    flexible-Prandtl correction of App. (PrandtlExtension), which is why that
+    collision is not built on them."""
+    v = orc.velocities().astype(float)
+    nu, rho, T, dT = 0.05, 1.0, 0.7, 0.01
+    p = orc.make_params(8, 8, nu=nu)
+    f, g, rc = orc.grad_populations(p, rho, 0.0, 0.0, T, [0, 0, 0, 0], [dT, 0.0], (0, 0), 0)
+    assert rc == 0
+    w, *_ = orc.equilibrium(0.0, 0.0, T)
+    Cv, Cp = 2.5, 3.5
+    feq = rho * w
+    geq = (2 * Cv - 2) * T * feq
+    q = -rho * Cp * nu * dT
+    qg = 0.5 * ((g - geq) * v[:, 0]).sum()
+    qf = 0.5 * ((f - feq) * v[:, 0] * (v ** 2).sum(1)).sum()
+    assert qg / q == pytest.approx((2 * Cv - 2) * T * T / Cp, rel=1e-12)
+    assert -0.3 < qf / q < -0.25
+    assert 0.1 < (qf + qg) / q < 0.2
