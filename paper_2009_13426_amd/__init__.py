@@ -74,7 +74,8 @@ class Sim:
                  **kw):
         """schedule: None (library default), a dict of lbm_schedule fields,
         or "auto" (the autotuner's cached choice for this size class,
-        tuned on a miss)."""
+        tuned on a miss; the library default for the four-constraint set,
+        which is built for that schedule only)."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -97,9 +98,13 @@ class Sim:
                                          C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx))
             _check(st, "lbm_create")
         if schedule == "auto":
-            from . import autotune
-            schedule = autotune.schedule_for(kw.get("precision", "fp64"), nx, ny,
-                                             device=self.device)
+            # the four-constraint kernels are built for the default schedule only
+            if int(kw.get("constraints", 8)) != 8:
+                schedule = None
+            else:
+                from . import autotune
+                schedule = autotune.schedule_for(kw.get("precision", "fp64"), nx, ny,
+                                                 device=self.device)
         if schedule:
             self.schedule = schedule
 

@@ -743,10 +743,14 @@ lbm_status lbm_step_graph_async(lbm_ctx* c, int32_t nsteps, int32_t chunk) {
     hipLaunchKernelGGL(set_step_base_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
                        static_cast<unsigned long long>(c->steps_done - parity));
     HIP_TRY(hipGetLastError());
-    for (int32_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(G.exec, c->stream));
+    // the base goes back to 0 even if a replay fails to enqueue, so that
+    // plain launches afterwards record their own step numbers
+    int32_t done = 0;
+    while (done < reps && hipGraphLaunch(G.exec, c->stream) == hipSuccess) ++done;
     hipLaunchKernelGGL(set_step_base_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(), 0ull);
+    c->steps_done += static_cast<int64_t>(done) * chunk;
+    if (done < reps) return LBM_ERR_HIP;
     HIP_TRY(hipGetLastError());
-    c->steps_done += static_cast<int64_t>(reps) * chunk;
   }
   return lbm_step_async(c, nsteps - reps * chunk);
 }

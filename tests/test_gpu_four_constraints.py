@@ -65,6 +65,9 @@ def test_schedules_and_batches(lbm):
     wl = W.four_quadrant(64, 10)
     sim, _ = gpu_run(lbm, wl, 0, "fp32", constraints=4)
     assert sim.schedule["step_block"] == 64
+    auto = lbm.Sim.from_workload(wl, precision="fp32", constraints=4, schedule="auto")
+    assert auto.schedule == sim.schedule
+    auto.close()
     for bad in (dict(step_block=128), dict(tiles_per_block=2)):
         with pytest.raises(lbm.LBMError) as e:
             sim.schedule = bad
