@@ -63,7 +63,12 @@ typedef enum {
 typedef enum {
   LBM_SHIFT_ADAPTIVE = 0,    /* eq. (criterion), optional hysteresis half-width */
   LBM_SHIFT_FIXED = 1,       /* one lattice (fixed_ux, fixed_uy) everywhere */
-  LBM_SHIFT_STATIC = 2       /* per-node map given to lbm_init_fields_static */
+  LBM_SHIFT_STATIC = 2,      /* per-node map given to lbm_init_fields_static */
+  LBM_SHIFT_NEIGHBOURHOOD = 3 /* overlapping ranges of half-width shift_halfwidth (< 1);
+                                 among the admissible shifts, the one most of the four
+                                 nearest neighbours use (Sec. III.A.2), ties to the
+                                 node's own, then to eq. (criterion).  8 constraints,
+                                 default schedule, not in lbm_step_batched */
 } lbm_shift_mode;
 
 typedef struct {

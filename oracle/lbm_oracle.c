@@ -345,10 +345,60 @@ int orc_select(double u, int Uprev, double halfwidth) {
   return select_axis(u, Uprev, halfwidth);
 }
 
+/* Reading of the neighbourhood choice among overlapping ranges (Sec.
+ * III.A.2: where the ranges of half-width w > 1/2 overlap, the shift can be
+ * chosen by the cell's neighbourhood to reduce the number of interface
+ * cells).  Per axis the admissible shifts are the n with n - w < u <= n + w
+ * (one or two of them for w < 1); among the admissible pairs the node takes
+ * the one that the most of its four nearest neighbours are colliding in at
+ * this step; ties go to its own current lattice, then to the plain
+ * criterion ceil(u - 1/2), then to the first pair in the order of
+ * increasing x and then y shift. */
+static void select_neighbourhood(const orc_sim* s, long n, double ux, double uy, int* nUx,
+                                 int* nUy) {
+  const orc_params* p = &s->p;
+  const double w = p->halfwidth;
+  long nx = p->nx, ny = p->ny;
+  long x = n % nx, y = n / nx;
+  long nb[4] = {y * nx + wrap(x + 1, nx), y * nx + wrap(x - 1, nx),
+                wrap(y + 1, ny) * nx + x, wrap(y - 1, ny) * nx + x};
+  int cand[2][2], nc[2];
+  double u[2] = {ux, uy};
+  for (int a = 0; a < 2; ++a) {
+    int c = (int)ceil(u[a] - 0.5);
+    nc[a] = 0;
+    for (int d = -1; d <= 1; ++d) {
+      int m = c + d;
+      if (u[a] > m - w && u[a] <= m + w) cand[a][nc[a]++] = m;
+    }
+  }
+  int Ux = s->Un[2 * n], Uy = s->Un[2 * n + 1];
+  int cx0 = (int)ceil(ux - 0.5), cy0 = (int)ceil(uy - 0.5);
+  int best = -1, bx = 0, by = 0;
+  for (int i = 0; i < nc[0]; ++i)
+    for (int j = 0; j < nc[1]; ++j) {
+      int cx = cand[0][i], cy = cand[1][j];
+      int score = 0;
+      for (int k = 0; k < 4; ++k)
+        score += (s->Un[2 * nb[k]] == cx && s->Un[2 * nb[k] + 1] == cy);
+      /* rank: neighbours first, then history, then the plain criterion */
+      int rank = 4 * score + 2 * (cx == Ux && cy == Uy) + (cx == cx0 && cy == cy0);
+      if (rank > best) {
+        best = rank;
+        bx = cx;
+        by = cy;
+      }
+    }
+  *nUx = bx;
+  *nUy = by;
+}
+
 orc_sim* orc_create(const orc_params* p) {
   if (!p || p->nx < 1 || p->ny < 1 || !(p->gamma > 1.0) || !(p->nu >= 0.0) ||
       p->newton_max_iter < 1 || !(p->halfwidth >= 0.5) ||
-      (p->constraints != 0 && p->constraints != 4 && p->constraints != 8))
+      (p->constraints != 0 && p->constraints != 4 && p->constraints != 8) ||
+      p->shift_mode < 0 || p->shift_mode > 3 ||
+      (p->shift_mode == 3 && !(p->halfwidth < 1.0)))
     return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   if (!s) return NULL;
@@ -455,6 +505,8 @@ static int collide_all(orc_sim* s) {
     } else if (p->shift_mode == 2) {
       nUx = s->Us[2 * n];
       nUy = s->Us[2 * n + 1];
+    } else if (p->shift_mode == 3) {
+      select_neighbourhood(s, n, ux, uy, &nUx, &nUy);
     } else {
       nUx = select_axis(ux, Ux, p->halfwidth);
       nUy = select_axis(uy, Uy, p->halfwidth);

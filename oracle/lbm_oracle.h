@@ -40,7 +40,9 @@ typedef struct {
   double gamma;          /* heat capacity ratio; Cv = 1/(gamma-1), Cp = gamma Cv */
   double nu;             /* kinematic viscosity; tau = 1/2 + nu / T per node */
   int shift_mode;        /* 0: adaptive criterion; 1: one fixed lattice (fixed_ux, fixed_uy);
-                            2: static per-node map set by orc_set_static_shift */
+                            2: static per-node map set by orc_set_static_shift;
+                            3: overlapping ranges of half-width halfwidth (< 1),
+                               shift chosen by the four nearest neighbours */
   int fixed_ux, fixed_uy;
   double halfwidth;      /* 0.5 reproduces the criterion exactly; > 0.5 adds hysteresis */
   double newton_tol;     /* max |G_a| per unit density; 1e-12 */

@@ -14,14 +14,15 @@ from typing import Dict, Optional, Sequence
 from . import _lib
 from ._lib import (ERR_ARG, ERR_HIP, ERR_NEWTON, ERR_NONPHYSICAL, ERR_STATE,  # noqa: F401
                    ERR_WORKSPACE, FP32_STORE, FP64, OK, Q, SHIFT_ADAPTIVE, SHIFT_FIXED,
-                   SHIFT_STATIC)
+                   SHIFT_NEIGHBOURHOOD, SHIFT_STATIC)
 
 lib = _lib.load()
 
 PRECISIONS = {"fp64": FP64, "fp32": FP32_STORE, "fp32_store": FP32_STORE,
               FP64: FP64, FP32_STORE: FP32_STORE}
 SHIFT_MODES = {"adaptive": SHIFT_ADAPTIVE, "fixed": SHIFT_FIXED, "static": SHIFT_STATIC,
-               0: SHIFT_ADAPTIVE, 1: SHIFT_FIXED, 2: SHIFT_STATIC}
+               "neighbourhood": SHIFT_NEIGHBOURHOOD,
+               0: SHIFT_ADAPTIVE, 1: SHIFT_FIXED, 2: SHIFT_STATIC, 3: SHIFT_NEIGHBOURHOOD}
 
 
 class LBMError(RuntimeError):

@@ -10,7 +10,7 @@ HIST_BINS = 32
 
 OK, ERR_ARG, ERR_WORKSPACE, ERR_HIP, ERR_STATE, ERR_NEWTON, ERR_NONPHYSICAL = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32_STORE = 0, 1
-SHIFT_ADAPTIVE, SHIFT_FIXED, SHIFT_STATIC = 0, 1, 2
+SHIFT_ADAPTIVE, SHIFT_FIXED, SHIFT_STATIC, SHIFT_NEIGHBOURHOOD = 0, 1, 2, 3
 
 
 class Config(C.Structure):

@@ -157,6 +157,37 @@ __device__ __forceinline__ int select_axis(double u, int uprev, double hw) {
   return static_cast<int>(ceil(u - 0.5));
 }
 
+// Overlapping ranges of half-width hw in [1/2, 1) chosen by the
+// neighbourhood (Sec. III.A.2): per axis the admissible shifts are the n
+// with n - hw < u <= n + hw; among the admissible pairs, the one that the
+// most of the four nearest neighbours collide in (nb16: the Un halves of
+// their tags), ties to the node's own lattice, then to ceil(u - 1/2), then
+// to the first pair in increasing x and then y order.
+__device__ __forceinline__ void select_neighbourhood(double ux, double uy, int ucx, int ucy,
+                                                     const int (&nb16)[4], double hw, int& nx,
+                                                     int& ny) {
+  const int c0x = static_cast<int>(ceil(ux - 0.5)), c0y = static_cast<int>(ceil(uy - 0.5));
+  int best = -1;
+  nx = c0x;
+  ny = c0y;
+  for (int dx = -1; dx <= 1; ++dx) {
+    const int cx = c0x + dx;
+    if (!(ux > cx - hw && ux <= cx + hw)) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int cy = c0y + dy;
+      if (!(uy > cy - hw && uy <= cy + hw)) continue;
+      const int c16 = (cx & 0xFF) | ((cy & 0xFF) << 8);
+      const int score = (nb16[0] == c16) + (nb16[1] == c16) + (nb16[2] == c16) + (nb16[3] == c16);
+      const int rank = 4 * score + 2 * (cx == ucx && cy == ucy) + (dx == 0 && dy == 0);
+      if (rank > best) {
+        best = rank;
+        nx = cx;
+        ny = cy;
+      }
+    }
+  }
+}
+
 template <int k>
 __device__ __forceinline__ double weight_of(const Weights& w) {
   if constexpr (k == 0)
@@ -363,7 +394,7 @@ struct PullMap {
 // the node's own slot of the output buffer and are read from there.  The
 // tail prepares the next step: moments of this collision, the mask of the
 // next pull's rebuilt links, and the list of nodes that have any.
-template <typename S, bool STREAM, int BLOCK, int M>
+template <typename S, bool STREAM, int BLOCK, int M, bool NBH = false>
 __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   __shared__ S sh_pop[2 * kQ][BLOCK];
   // FP32 storage: the Newton solve keeps its last factors here for the
@@ -460,10 +491,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
                           fabs(upx) < 1e300 && fabs(upy) < 1e300;
     if (!physical) {
       code = kCodeNonphysical;
-    } else if (P.shift_mode == 0) {
-      // a4: lattice of the next pull
-      nux = select_axis(upx + unx, unx, P.halfwidth);
-      nuy = select_axis(upy + uny, uny, P.halfwidth);
+    } else if (NBH ? P.shift_mode == 3 : P.shift_mode == 0) {
+      // a4: lattice of the next pull (the neighbourhood choice, shift mode 3,
+      // is compiled into its own kernels: NBH)
+      if constexpr (!NBH) {
+        nux = select_axis(upx + unx, unx, P.halfwidth);
+        nuy = select_axis(upy + uny, uny, P.halfwidth);
+      } else {
+        const int ny_ = a.grid.ny;
+        int nb16[4];
+        nb16[0] = tag_un16(a.tin[static_cast<long long>(y) * nx + wrapc(x + 1, nx, a.grid.fast_x)]);
+        nb16[1] = tag_un16(a.tin[static_cast<long long>(y) * nx + wrapc(x - 1, nx, a.grid.fast_x)]);
+        nb16[2] = tag_un16(a.tin[static_cast<long long>(wrapc(y + 1, ny_, a.grid.fast_y)) * nx + x]);
+        nb16[3] = tag_un16(a.tin[static_cast<long long>(wrapc(y - 1, ny_, a.grid.fast_y)) * nx + x]);
+        select_neighbourhood(upx + unx, upy + uny, unx, uny, nb16, P.halfwidth, nux, nuy);
+      }
       if (abs(nux) > P.max_abs_shift || abs(nuy) > P.max_abs_shift) {
         code = kCodeNonphysical;
         nux = unx;  // keep every stored shift in range: later pulls stay in bounds
@@ -578,7 +620,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
 // TILED: each workgroup runs a.tiles consecutive tiles in a loop (the loop
 // keeps kernel arguments live across the body, which costs spills); else
 // one tile per workgroup.
-template <typename S, bool STREAM, int BLOCK, bool TILED, int M = kM>
+template <typename S, bool STREAM, int BLOCK, bool TILED, int M = kM, bool NBH = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void step_kernel(StepArgs a) {
   const int g = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -586,10 +628,10 @@ void step_kernel(StepArgs a) {
     for (int t = 0; t < a.tiles; ++t) {
       const int b = g * a.tiles + t;
       if (b >= a.ntiles) break;
-      step_body<S, STREAM, BLOCK, M>(a, b);
+      step_body<S, STREAM, BLOCK, M, NBH>(a, b);
     }
   } else {
-    step_body<S, STREAM, BLOCK, M>(a, g);
+    step_body<S, STREAM, BLOCK, M, NBH>(a, g);
   }
 }
 

@@ -53,7 +53,9 @@ bool config_ok(const lbm_config* c) {
   return c->nx >= 1 && c->ny >= 1 && N < (1ll << 31) && N * es < (1ll << 32) &&
          (c->precision == LBM_FP64 || c->precision == LBM_FP32_STORE) && c->gamma > 1.0 &&
          std::isfinite(c->gamma) && c->nu >= 0.0 && std::isfinite(c->nu) &&
-         c->shift_mode >= 0 && c->shift_mode <= 2 && c->shift_halfwidth >= 0.5 &&
+         c->shift_mode >= 0 && c->shift_mode <= 3 && c->shift_halfwidth >= 0.5 &&
+         (c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD ||
+          (c->shift_halfwidth < 1.0 && c->constraints == kM)) &&
          c->shift_halfwidth < 8.0 && c->newton_tol > 0.0 && c->newton_max_iter >= 1 &&
          c->newton_max_iter <= 1000 && c->max_abs_shift >= 0 && c->max_abs_shift <= 12 &&
          std::abs(c->fixed_ux) <= c->max_abs_shift && std::abs(c->fixed_uy) <= c->max_abs_shift &&
@@ -195,8 +197,17 @@ const void* step_fn_of(bool tiled) {
 // Device entry of the step kernel for a storage type, pass, block size,
 // tiling and constraint count; nullptr for a combination that is not built
 // (the four-constraint set is built for 64-lane untiled blocks only).
-const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled, int M) {
+const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled, int M,
+                           bool nbh = false) {
   const bool f64 = precision == LBM_FP64;
+  if (nbh) {  // shift mode 3: default schedule, 8 constraints
+    if (block != 64 || tiled || M != kM) return nullptr;
+    if (f64)
+      return stream_pass ? reinterpret_cast<const void*>(&step_kernel<double, true, 64, false, kM, true>)
+                         : reinterpret_cast<const void*>(&step_kernel<double, false, 64, false, kM, true>);
+    return stream_pass ? reinterpret_cast<const void*>(&step_kernel<float, true, 64, false, kM, true>)
+                       : reinterpret_cast<const void*>(&step_kernel<float, false, 64, false, kM, true>);
+  }
   if (M == 4) {
     if (block != 64 || tiled) return nullptr;
     if (f64)
@@ -297,7 +308,8 @@ Launch<StepArgs> step_launch(const lbm_ctx* c, int src, int dst, bool stream_pas
   a.ntiles = static_cast<int>((c->grid.N + B - 1) / B);
   a.tiles = stream_pass ? c->sched.tiles_per_block : 1;
   a.remap = stream_pass ? c->sched.xcd_remap : 1;
-  L.fn = step_kernel_fn(c->cfg.precision, stream_pass, B, a.tiles > 1, c->cfg.constraints);
+  L.fn = step_kernel_fn(c->cfg.precision, stream_pass, B, a.tiles > 1, c->cfg.constraints,
+                        c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD);
   L.grid = dim3(static_cast<unsigned>((a.ntiles + a.tiles - 1) / a.tiles));
   L.block = dim3(B);
   return L;
@@ -438,7 +450,8 @@ int default_rebuild_blocks(long long N) {
 bool schedule_ok(const lbm_ctx* c, const lbm_schedule* s) {
   if (!s) return false;
   const bool tiled = s->tiles_per_block > 1;
-  if (!step_kernel_fn(c->cfg.precision, true, s->step_block, tiled, c->cfg.constraints))
+  if (!step_kernel_fn(c->cfg.precision, true, s->step_block, tiled, c->cfg.constraints,
+                      c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD))
     return false;
   if (!step_batched_fn(c->cfg.precision, s->step_block, c->cfg.constraints)) return false;
   const long long tiles = (c->grid.N + s->step_block - 1) / s->step_block;
@@ -860,6 +873,7 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
   for (int32_t k = 0; k < n; ++k) {
     lbm_ctx* c = ctxs[k];
     if (!c || nsteps[k] < 0) return LBM_ERR_ARG;
+    if (c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD) return LBM_ERR_ARG;
     if (c->cfg.precision != ctxs[0]->cfg.precision ||
         c->cfg.constraints != ctxs[0]->cfg.constraints || c->stream != ctxs[0]->stream ||
         c->device != ctxs[0]->device)

@@ -108,7 +108,16 @@ CASES = {
     "sod_static_256": (lambda: W.sod_static_shift(256, 1, steps=32), 32),
     # without the sensor (viscosity high enough to run without it)
     "quadrant_100_nosensor": (lambda: _nosensor(W.four_quadrant(100, 40), 3e-3), 40),
+    # overlapping shift ranges chosen by the neighbourhood (half-width 0.9)
+    "quadrant_100_neighbourhood": (lambda: _neighbourhood(W.four_quadrant(100, 40)), 40),
+    "vortex_100_neighbourhood": (lambda: _neighbourhood(W.isentropic_vortex(100, steps=40)), 40),
 }
+
+
+def _neighbourhood(wl, halfwidth=0.9):
+    wl.shift_mode = 3
+    wl.halfwidth = halfwidth
+    return wl
 
 
 def _nosensor(wl, nu):
@@ -262,3 +271,16 @@ def test_batched_equals_alone(lbm, precision):
     for s, (fa, ga) in zip(sims, alone):
         fb, gb = s.populations()
         assert bool((fa == fb).all()) and bool((ga == gb).all())
+
+
+def test_neighbourhood_choice_takes_the_oracles_decisions(lbm, orc):
+    """Same lattice decisions as the oracle's neighbourhood rule: equal
+    numbers of rebuilt links over the run, equal lattice tags at the end."""
+    wl = _neighbourhood(W.four_quadrant(96, 30))
+    o, ref = oracle_run(orc, wl, 30)
+    sim, got = gpu_run(lbm, wl, 30, "fp64", stats=True)
+    d = sim.diag()
+    print(f"neighbourhood: rebuilt links gpu {d['mismatched_links']} "
+          f"oracle {o.stats()['mismatched_links']}", flush=True)
+    assert d["mismatched_links"] == o.stats()["mismatched_links"]
+    assert np.array_equal(got["Ux"], ref["Ucx"]) and np.array_equal(got["Uy"], ref["Ucy"])

@@ -200,3 +200,17 @@ def test_copied_state_continues_bitwise(lbm, precision):
     assert e.value.status == lbm.ERR_STATE
     for s in (a, b, c, fresh):
         s.close()
+
+
+def test_neighbourhood_mode_runs_the_default_schedule_only(lbm):
+    wl = W.four_quadrant(48, 4)
+    wl.shift_mode, wl.halfwidth = 3, 0.9
+    sim = lbm.Sim.from_workload(wl, precision="fp32")
+    with pytest.raises(lbm.LBMError) as e:
+        sim.schedule = dict(step_block=128)
+    assert e.value.status == lbm.ERR_ARG
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.step_batched([sim], [2])
+    assert e.value.status == lbm.ERR_ARG
+    sim.step_graph(8, 4)                      # graphs are fine
+    sim.close()

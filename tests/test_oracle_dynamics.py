@@ -284,3 +284,44 @@ def test_printed_heat_flux_terms_carry_a_fraction_of_q(orc):
     assert qg / q == pytest.approx((2 * Cv - 2) * T * T / Cp, rel=1e-12)
     assert -0.3 < qf / q < -0.25
     assert 0.1 < (qf + qg) / q < 0.2
+
+
+def test_neighbourhood_choice_without_overlap_is_the_criterion(orc):
+    """With half-width 1/2 the ranges do not overlap, every axis has one
+    admissible shift, and the neighbourhood choice is eq. (criterion)."""
+    wl = W.four_quadrant(40, 12)
+    a = orc.Sim.from_workload(wl, shift_mode=0, halfwidth=0.5)
+    b = orc.Sim.from_workload(wl, shift_mode=3, halfwidth=0.5)
+    a.step(12)
+    b.step(12)
+    ma, mb = a.macros(), b.macros()
+    for k in ("rho", "ux", "uy", "T", "Ucx", "Ucy", "Unx", "Uny"):
+        assert np.array_equal(ma[k], mb[k]), k
+
+
+def test_neighbourhood_choice_reduces_interface_cells(orc):
+    """Sec. III.A.2: with overlapping ranges the shift can be chosen by the
+    neighbourhood to reduce the number of interface cells.  On the seeded
+    quadrant flow with half-width 0.9 it leaves fewer nodes next to another
+    lattice than the history choice, and rebuilds fewer links."""
+    wl = W.four_quadrant(100, 60)
+
+    def run(mode):
+        s = orc.Sim.from_workload(wl, shift_mode=mode, halfwidth=0.9)
+        s.step(60)
+        m = s.macros()
+        cx, cy = m["Ucx"], m["Ucy"]
+        diff = np.zeros(cx.shape, bool)
+        for ax in (0, 1):
+            for sh in (1, -1):
+                diff |= (cx != np.roll(cx, sh, ax)) | (cy != np.roll(cy, sh, ax))
+        return int(diff.sum()), s.stats()["mismatched_links"]
+
+    hist, nb = run(0), run(3)
+    assert nb[0] < 0.9 * hist[0], (hist, nb)
+    assert nb[1] < hist[1], (hist, nb)
+
+
+def test_neighbourhood_choice_needs_overlap_below_one(orc):
+    with pytest.raises(ValueError):
+        orc.Sim(8, 8, shift_mode=3, halfwidth=1.0)
