@@ -29,7 +29,7 @@ STEP_BLOCKS = {"fp64": (64, 128), "fp32": (64, 128, 256)}
 TILES = (1, 2, 4)
 REMAPS = (1, 0)
 REBUILD_BLOCKS = (0, 256, 1024, 8192)
-MARGIN = 0.01   # relative gain a candidate needs over the best so far
+MARGIN = 0.02   # relative gain a candidate needs over the best so far
 
 
 def default_cache_path() -> str:

@@ -62,8 +62,8 @@ def test_choice_is_the_fastest_step_then_the_fastest_rebuild():
 
 def test_noise_below_the_margin_keeps_the_first_candidate():
     def timer(sim, sched, steps, repeats, reset):
-        # the second candidate is 0.5 % faster: within the margin
-        return 0.2, 1.0 - (0.005 if sched["xcd_remap"] == 0 and sched["step_block"] == 64
+        # the second candidate is 1.5 % faster: within the margin
+        return 0.2, 1.0 - (0.015 if sched["xcd_remap"] == 0 and sched["step_block"] == 64
                            and sched["tiles_per_block"] == 1 else 0.0)
     out = A.choose(FakeSim(), "fp64", timer=timer)
     assert out["schedule"]["step_block"] == 64 and out["schedule"]["xcd_remap"] == 1

@@ -173,3 +173,30 @@ def test_advected_sod_2048x4_full(lbm, orc, precision):
             {k: ref[k].ravel() for k in ("rho", "ux", "uy", "T")},
             precision, wl.sensor, f"advected_sod_2048x4/{precision}/{steps}",
             fp64_bounds=(1e-9, 1e-11))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_bench_launch_configuration_is_bitwise_the_plain_one(lbm, precision, tmp_path,
+                                                           monkeypatch):
+    """bench.py times the 4096^2 draw under the autotuner's schedule with the
+    step loop replayed as HIP graphs of 10 steps; the sampled parity above
+    runs plain launches under the default schedule.  The two give the same
+    fields bit for bit (every schedule and graph replay runs the same
+    per-node code), so the parity there holds for the timed configuration."""
+    from paper_2009_13426_amd import autotune
+    monkeypatch.setenv(autotune.CACHE_ENV, str(tmp_path / "schedules.json"))
+    wl = W.four_quadrant(4096, 30)
+    entry = autotune.tune_workload(W.four_quadrant(4096, 120), precision=precision, steps=3,
+                                   repeats=1, advance=20)
+    print(f"{precision}: tuned schedule {entry['schedule']}", flush=True)
+    a = lbm.Sim.from_workload(wl, precision=precision, schedule="auto")
+    a.step(10)                      # warm-up as in bench.py, then graph replays
+    a.step_graph(20, 10)
+    ma = {k: v.cpu().numpy() for k, v in a.macros().items()}
+    a.close()
+    b = lbm.Sim.from_workload(wl, precision=precision)
+    b.step(30)
+    mb = {k: v.cpu().numpy() for k, v in b.macros().items()}
+    b.close()
+    for k in ("rho", "ux", "uy", "T", "Ux", "Uy"):
+        assert np.array_equal(ma[k], mb[k]), k
