@@ -73,3 +73,32 @@ def test_host_side_calls_without_gpu(so):
     assert sorted(zip(cx, cy)) == sorted(
         [(0, 0)] + [(a * s, b * s) for a, b in [(1, 0), (0, 1), (1, 1), (1, -1), (2, 0), (0, 2),
                                                  (2, 2), (2, -2), (3, 0), (0, 3)] for s in (1, -1)])
+
+
+def test_size_limits_and_invalid_configs(so):
+    """Planes are addressed with 32-bit byte offsets: a configuration whose
+    plane would reach 4 GiB is refused (workspace size 0), as are empty grids
+    and out-of-range options; the largest accepted planes are just below."""
+    from paper_2009_13426_amd import _lib
+    L = _lib.load()
+
+    def size(nx, ny, **kw):
+        cfg = _lib.Config()
+        L.lbm_default_config(ctypes.byref(cfg), nx, ny)
+        for k, v in kw.items():
+            setattr(cfg, k, v)
+        return L.lbm_workspace_bytes(ctypes.byref(cfg))
+
+    assert size(32768, 16384) == 0                      # FP64: 2^29 nodes x 8 B = 4 GiB
+    assert size(32768, 16383) > 0
+    assert size(32768, 32768, precision=1) == 0         # FP32: 2^30 nodes x 4 B = 4 GiB
+    assert size(32768, 32767, precision=1) > 0
+    assert size(0, 5) == 0 and size(5, 0) == 0
+    assert size(1, 1) > 0
+    assert size(8, 8, shift_mode=4) == 0
+    assert size(8, 8, shift_mode=3, shift_halfwidth=1.0) == 0
+    assert size(8, 8, shift_mode=3, shift_halfwidth=0.9) > 0
+    assert size(8, 8, shift_mode=3, shift_halfwidth=0.9, constraints=4) == 0
+    assert size(8, 8, constraints=5) == 0 and size(8, 8, constraints=4) > 0
+    assert size(8, 8, newton_max_iter=0) == 0
+    assert size(8, 8, max_abs_shift=13) == 0

@@ -284,3 +284,21 @@ def test_neighbourhood_choice_takes_the_oracles_decisions(lbm, orc):
           f"oracle {o.stats()['mismatched_links']}", flush=True)
     assert d["mismatched_links"] == o.stats()["mismatched_links"]
     assert np.array_equal(got["Ux"], ref["Ucx"]) and np.array_equal(got["Uy"], ref["Ucy"])
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 3), (5, 1), (1, 7), (9, 4)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tiny_grids(lbm, orc, shape, precision):
+    """Grids narrower than the pull reach (3 + |U|) and the gradient stencil:
+    every offset wraps several times around the period (the kernels' modulo
+    path); a 1 x 1 grid pulls every population from itself."""
+    nx, ny = shape
+    wl = W.smooth_random(nx, ny, seed=11, amp=(0.05, 0.6, 0.6, 0.05),
+                         base=(1.0, 0.45, -0.4, 0.7), steps=25, nu=5e-3)
+    _, ref = oracle_run(orc, wl, 25)
+    sim, got = gpu_run(lbm, wl, 25, precision)
+    check(orc, got, ref, TOL[precision], f"tiny {nx}x{ny}/{precision}")
+    shift_disagreement(got, ref)
+    sim.step(0)                      # an empty call changes nothing
+    again = {k: v.cpu().numpy() for k, v in sim.macros().items()}
+    assert all(np.array_equal(again[k], got[k]) for k in ("rho", "ux", "uy", "T"))
