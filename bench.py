@@ -147,7 +147,7 @@ def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
                        f"{n} steps, FP64, {dt:.1f} s")
 
 
-SERVE_JOBS = 32
+SERVE_JOBS = 128
 
 
 def serving_pass(torch, W, n_jobs=SERVE_JOBS, quantum=50, schedule="auto"):
