@@ -75,8 +75,9 @@ class Sim:
                  **kw):
         """schedule: None (library default), a dict of lbm_schedule fields,
         or "auto" (the autotuner's cached choice for this size class,
-        tuned on a miss; the library default for the four-constraint set,
-        which is built for that schedule only)."""
+        tuned on a miss; the library default for the four-constraint set
+        and the neighbourhood shift choice, which are built for that
+        schedule only)."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -99,8 +100,10 @@ class Sim:
                                          C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx))
             _check(st, "lbm_create")
         if schedule == "auto":
-            # the four-constraint kernels are built for the default schedule only
-            if int(kw.get("constraints", 8)) != 8:
+            # the four-constraint and neighbourhood-choice kernels are built
+            # for the default schedule only
+            if int(kw.get("constraints", 8)) != 8 or \
+                    SHIFT_MODES[kw.get("shift_mode", "adaptive")] == SHIFT_NEIGHBOURHOOD:
                 schedule = None
             else:
                 from . import autotune

@@ -213,4 +213,7 @@ def test_neighbourhood_mode_runs_the_default_schedule_only(lbm):
         lbm.step_batched([sim], [2])
     assert e.value.status == lbm.ERR_ARG
     sim.step_graph(8, 4)                      # graphs are fine
+    auto = lbm.Sim.from_workload(wl, precision="fp32", schedule="auto")
+    assert auto.schedule["step_block"] == 64
+    auto.close()
     sim.close()
