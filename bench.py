@@ -126,11 +126,11 @@ def stats_pass(lbm, wl, precision, steps):
 
 def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
     """The FP64 oracle, as it is, on a bounded sample of the same workload:
-    a 511 x 511 periodic crop around the quadrant corner, stepped until about
+    a 641 x 641 periodic crop around the quadrant corner, stepped until about
     seconds_target have passed (at most max_steps, which keeps the crop
     clear of the wave collisions its smaller periodic box would bring)."""
     import oracle
-    half = 255
+    half = 320
     sample = wl_full.window(wl_full.nx // 2, wl_full.ny // 2, half)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     s = oracle.Sim.from_workload(sample)
