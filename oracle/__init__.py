@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_oracle.so")
 
 Q = 21
+Q49 = 49
 M = 8
 OK, ERR_ARG, ERR_NEWTON, ERR_NONPHYSICAL = 0, -1, -5, -6
 HIST = 128
@@ -49,6 +50,9 @@ def lib():
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
         L.orc_velocities.argtypes = [ip, ip]
+        L.orc_velocities_q.argtypes = [C.c_int, ip, ip]
+        L.orc_lattice_of.argtypes = [C.c_int]
+        L.orc_lattice_of.restype = C.c_int
         L.orc_equilibrium.argtypes = [C.c_double, C.c_double, C.c_double, dp,
                                       C.c_double, C.c_int, dp, dp, ip]
         L.orc_equilibrium.restype = C.c_int
@@ -88,11 +92,17 @@ def _ip(a):
     return a.ctypes.data_as(C.POINTER(C.c_int))
 
 
-def velocities():
-    cx = np.zeros(Q, np.int32)
-    cy = np.zeros(Q, np.int32)
-    lib().orc_velocities(_ip(cx), _ip(cy))
+def velocities(lattice=Q):
+    """Integer velocities of D2Q21 (default) or D2Q49, one row each."""
+    cx = np.zeros(lattice, np.int32)
+    cy = np.zeros(lattice, np.int32)
+    lib().orc_velocities_q(int(lattice), _ip(cx), _ip(cy))
     return np.stack([cx, cy], 1)
+
+
+def lattice_of(constraints):
+    """Lattice a constraint set is solved on: 49 for 13, else 21."""
+    return lib().orc_lattice_of(int(constraints))
 
 
 def targets(ux, uy, T):
@@ -103,8 +113,9 @@ def targets(ux, uy, T):
 
 def equilibrium(ux, uy, T, lam0=None, tol=1e-12, max_iter=100, constraints=M):
     """Weights w (per unit density), multipliers, iterations, status.
-    constraints: 8 (eq. 8moments) or 4 (mass, momentum, energy)."""
-    w = np.zeros(Q)
+    constraints: 8 (eq. 8moments), 4 (mass, momentum, energy) or 13 (the
+    reference model on D2Q49; w then holds 49 weights)."""
+    w = np.zeros(lattice_of(constraints))
     lam = np.zeros(constraints)
     it = C.c_int(0)
     l0 = None
@@ -134,8 +145,9 @@ def make_params(nx, ny, gamma=1.4, nu=1e-3, shift_mode=0, fixed_U=(0, 0),
 
 
 def grad_populations(params: Params, rho, ux, uy, T, du, dT, L, post):
-    f = np.zeros(Q)
-    g = np.zeros(Q)
+    q = lattice_of(params.constraints)
+    f = np.zeros(q)
+    g = np.zeros(q)
     du = np.ascontiguousarray(du, dtype=np.float64)
     dT = np.ascontiguousarray(dT, dtype=np.float64)
     rc = lib().orc_grad_populations(C.byref(params), rho, ux, uy, T, _dp(du), _dp(dT),
@@ -155,6 +167,7 @@ class Sim:
     def __init__(self, nx, ny, **kw):
         self.nx, self.ny = nx, ny
         self.params = make_params(nx, ny, **kw)
+        self.Q = lattice_of(self.params.constraints)
         self._h = lib().orc_create(C.byref(self.params))
         if not self._h:
             raise ValueError("invalid oracle parameters")
@@ -203,10 +216,10 @@ class Sim:
 
     def populations(self):
         N = self.nx * self.ny
-        f = np.zeros(Q * N)
-        g = np.zeros(Q * N)
+        f = np.zeros(self.Q * N)
+        g = np.zeros(self.Q * N)
         lib().orc_populations(self._h, _dp(f), _dp(g))
-        return f.reshape(Q, self.ny, self.nx), g.reshape(Q, self.ny, self.nx)
+        return f.reshape(self.Q, self.ny, self.nx), g.reshape(self.Q, self.ny, self.nx)
 
     def conserved(self):
         out = np.zeros(4)

@@ -1,5 +1,6 @@
 /*
- * Plain FP64 CPU oracle of the adaptive D2Q21 compressible LBM
+ * Plain FP64 CPU oracle of the adaptive D2Q21 compressible LBM (and of the
+ * paper's reference model, D2Q49 with 13 constraints)
  * (Coreixas & Latt, arXiv 2009.13426).  TEST INFRASTRUCTURE ONLY: see
  * lbm_oracle.h.  Each function follows the passage of the paper cited above
  * it; readings of passages the paper leaves open are marked "Reading".
@@ -35,12 +36,23 @@ static const int XI[ORC_Q][2] = {
     {2, 2},  {-2, 2},  {-2, -2}, {2, -2},
     {3, 0},  {-3, 0},  {0, 3},  {0, -3}};
 
-void orc_velocities(int* cx, int* cy) {
-  for (int i = 0; i < ORC_Q; ++i) {
-    cx[i] = XI[i][0];
-    cy[i] = XI[i][1];
+/* D2Q49 (Sec. I and App. C, the paper's reference lattice): the tensor
+ * product {-3, ..., 3}^2, velocity i = (i mod 7 - 3, i div 7 - 3). */
+static int cx_of(int Q, int i) { return Q == ORC_Q49 ? i % 7 - 3 : XI[i][0]; }
+static int cy_of(int Q, int i) { return Q == ORC_Q49 ? i / 7 - 3 : XI[i][1]; }
+
+/* Lattice of a constraint count: the 13-constraint set is solved on D2Q49,
+ * the 8- and 4-constraint sets on D2Q21. */
+int orc_lattice_of(int M) { return M == 13 ? ORC_Q49 : ORC_Q; }
+
+void orc_velocities_q(int Q, int* cx, int* cy) {
+  for (int i = 0; i < Q; ++i) {
+    cx[i] = cx_of(Q, i);
+    cy[i] = cy_of(Q, i);
   }
 }
+
+void orc_velocities(int* cx, int* cy) { orc_velocities_q(ORC_Q, cx, cy); }
 
 /* ------------------------------------------------ numerical equilibrium
  * Eq. (feqNum_8Mom): f_i^eq = rho exp[-(1 + lambda . phi(xi_i))] with the
@@ -50,8 +62,7 @@ void orc_velocities(int* cx, int* cy) {
  * with the integer-valued xi_i and the peculiar velocity u - U; the span of
  * phi is invariant under integer translations, so this is the same
  * equilibrium as the one written with c_i = xi_i + U and u. */
-static void basis8(int i, double phi[ORC_M]) {
-  double x = XI[i][0], y = XI[i][1];
+static void basis8(double x, double y, double phi[ORC_MMAX]) {
   double s = x * x + y * y;
   phi[0] = 1.0;
   phi[1] = x;
@@ -65,19 +76,48 @@ static void basis8(int i, double phi[ORC_M]) {
 
 /* Sec. "Reduced models", eq. (feqNum_4Mom): the four constraints of mass,
  * momentum and total energy, phi = (1, xi_x, xi_y, |xi|^2). */
-static void basis4(int i, double phi[ORC_M]) {
-  double x = XI[i][0], y = XI[i][1];
+static void basis4(double x, double y, double phi[ORC_MMAX]) {
   phi[0] = 1.0;
   phi[1] = x;
   phi[2] = y;
   phi[3] = x * x + y * y;
 }
 
-static void basis(int M, int i, double phi[ORC_M]) {
+/* App. C, eqs. (G0)-(G4yyaa) and (feqNum_13Mom): the 13 constraints of the
+ * reference model, up to the third-order moments and the contracted
+ * fourth-order ones, phi = (1, xi_x, xi_y, xi_x^2, xi_x xi_y, xi_y^2,
+ * xi_x^3, xi_x^2 xi_y, xi_x xi_y^2, xi_y^3, xi_x^2 |xi|^2, xi_x xi_y |xi|^2,
+ * xi_y^2 |xi|^2).  Reading: the printed exponent of eq. (feqNum_13Mom) lists
+ * twelve multipliers and leaves out the one of xi_x^3, although G_3,xxx is
+ * among the constraints; it is taken as a dropped term (13 constraints, 13
+ * multipliers). */
+static void basis13(double x, double y, double phi[ORC_MMAX]) {
+  double s = x * x + y * y;
+  phi[0] = 1.0;
+  phi[1] = x;
+  phi[2] = y;
+  phi[3] = x * x;
+  phi[4] = x * y;
+  phi[5] = y * y;
+  phi[6] = x * x * x;
+  phi[7] = x * x * y;
+  phi[8] = x * y * y;
+  phi[9] = y * y * y;
+  phi[10] = x * x * s;
+  phi[11] = x * y * s;
+  phi[12] = y * y * s;
+}
+
+/* Monomials of velocity i of the lattice of constraint set M. */
+static void basis(int M, int i, double phi[ORC_MMAX]) {
+  int Q = orc_lattice_of(M);
+  double x = cx_of(Q, i), y = cy_of(Q, i);
   if (M == 4)
-    basis4(i, phi);
+    basis4(x, y, phi);
+  else if (M == 13)
+    basis13(x, y, phi);
   else
-    basis8(i, phi);
+    basis8(x, y, phi);
 }
 
 /* Constraint targets per unit density, eqs. (G0_8mom)-(G3yaa_8mom), with the
@@ -89,6 +129,22 @@ void orc_targets_m(int M, double ux, double uy, double T, double* m) {
     m[1] = ux;
     m[2] = uy;
     m[3] = 2.0 * E;
+    return;
+  }
+  if (M == 13) { /* eqs. (G0)-(G4yyaa) */
+    m[0] = 1.0;
+    m[1] = ux;
+    m[2] = uy;
+    m[3] = ux * ux + T;
+    m[4] = ux * uy;
+    m[5] = uy * uy + T;
+    m[6] = ux * (ux * ux + 3.0 * T);
+    m[7] = (ux * ux + T) * uy;
+    m[8] = ux * (uy * uy + T);
+    m[9] = uy * (uy * uy + 3.0 * T);
+    m[10] = 2.0 * ((E + 2.0 * T) * ux * ux + (E + T) * T);
+    m[11] = 2.0 * (E + 2.0 * T) * ux * uy;
+    m[12] = 2.0 * ((E + 2.0 * T) * uy * uy + (E + T) * T);
     return;
   }
   m[0] = 1.0;
@@ -109,12 +165,13 @@ void orc_targets(double ux, double uy, double T, double* m) { orc_targets_m(8, u
  * whose Hessian is H = sum_i w_i phi phi^T (positive definite since phi has
  * rank 8 on the lattice).  Minimising Psi is the entropy problem of
  * eqs. (Hfunction)-(exponential) with prefactor a = rho. */
-static double evaluate(int M, const double lam[ORC_M], const double m[ORC_M],
-                       double w[ORC_Q], double G[ORC_M]) {
-  double phi[ORC_M];
+static double evaluate(int M, const double lam[ORC_MMAX], const double m[ORC_MMAX],
+                       double w[ORC_QMAX], double G[ORC_MMAX]) {
+  double phi[ORC_MMAX];
   double psi = 0.0;
+  const int Q = orc_lattice_of(M);
   for (int a = 0; a < M; ++a) G[a] = -m[a];
-  for (int i = 0; i < ORC_Q; ++i) {
+  for (int i = 0; i < Q; ++i) {
     basis(M, i, phi);
     double e = 1.0;
     for (int a = 0; a < M; ++a) e += lam[a] * phi[a];
@@ -126,10 +183,11 @@ static double evaluate(int M, const double lam[ORC_M], const double m[ORC_M],
   return psi;
 }
 
-static void hessian(int M, const double w[ORC_Q], double H[ORC_M][ORC_M]) {
-  double phi[ORC_M];
-  memset(H, 0, sizeof(double) * ORC_M * ORC_M);
-  for (int i = 0; i < ORC_Q; ++i) {
+static void hessian(int M, const double w[ORC_QMAX], double H[ORC_MMAX][ORC_MMAX]) {
+  double phi[ORC_MMAX];
+  const int Q = orc_lattice_of(M);
+  memset(H, 0, sizeof(double) * ORC_MMAX * ORC_MMAX);
+  for (int i = 0; i < Q; ++i) {
     basis(M, i, phi);
     for (int a = 0; a < M; ++a)
       for (int b = 0; b < M; ++b) H[a][b] += w[i] * phi[a] * phi[b];
@@ -137,8 +195,9 @@ static void hessian(int M, const double w[ORC_Q], double H[ORC_M][ORC_M]) {
 }
 
 /* Gaussian elimination with partial pivoting for H d = G (leading M x M). */
-static int solve(int M, double Hin[ORC_M][ORC_M], const double G[ORC_M], double d[ORC_M]) {
-  double A[ORC_M][ORC_M + 1];
+static int solve(int M, double Hin[ORC_MMAX][ORC_MMAX], const double G[ORC_MMAX],
+                 double d[ORC_MMAX]) {
+  double A[ORC_MMAX][ORC_MMAX + 1];
   for (int r = 0; r < M; ++r) {
     for (int c = 0; c < M; ++c) A[r][c] = Hin[r][c];
     A[r][M] = G[r];
@@ -179,15 +238,16 @@ static double maxabs(const double* v, int n) {
 /* Initial guess: the lattice-normalised Maxwellian, lambda_1 = -u/T,
  * lambda_2 = I / (2T) (for M = 4 the |xi|^2 multiplier 1/(2T)), cross and
  * third-order multipliers zero, lambda_0 such that sum_i w_i = 1. */
-static void maxwellian_guess(int M, double ux, double uy, double T, double lam[ORC_M]) {
-  double phi[ORC_M];
-  for (int a = 0; a < ORC_M; ++a) lam[a] = 0.0;
+static void maxwellian_guess(int M, double ux, double uy, double T, double lam[ORC_MMAX]) {
+  double phi[ORC_MMAX];
+  const int Q = orc_lattice_of(M);
+  for (int a = 0; a < ORC_MMAX; ++a) lam[a] = 0.0;
   lam[1] = -ux / T;
   lam[2] = -uy / T;
   lam[3] = 0.5 / T;
-  if (M == 8) lam[5] = 0.5 / T;
+  if (M != 4) lam[5] = 0.5 / T;
   double z = 0.0;
-  for (int i = 0; i < ORC_Q; ++i) {
+  for (int i = 0; i < Q; ++i) {
     basis(M, i, phi);
     double e = 0.0;
     for (int a = 1; a < M; ++a) e += lam[a] * phi[a];
@@ -205,14 +265,14 @@ static void maxwellian_guess(int M, double ux, double uy, double T, double lam[O
  * Reading: the polishing step. */
 int orc_equilibrium_m(int M, double ux, double uy, double T, const double* lam0,
                       double tol, int max_iter, double* w, double* lam, int* iters) {
-  double m[ORC_M], l[ORC_M], G[ORC_M], d[ORC_M], H[ORC_M][ORC_M];
-  double wt[ORC_Q], lt[ORC_M], Gt[ORC_M];
+  double m[ORC_MMAX], l[ORC_MMAX], G[ORC_MMAX], d[ORC_MMAX], H[ORC_MMAX][ORC_MMAX];
+  double wt[ORC_QMAX], lt[ORC_MMAX], Gt[ORC_MMAX];
   if (iters) *iters = 0;
-  if (M != 4 && M != 8) return ORC_ERR_ARG;
+  if (M != 4 && M != 8 && M != 13) return ORC_ERR_ARG;
   if (!(T > 0.0) || !isfinite(T) || !isfinite(ux) || !isfinite(uy))
     return ORC_ERR_NONPHYSICAL;
   orc_targets_m(M, ux, uy, T, m);
-  for (int a = 0; a < ORC_M; ++a) l[a] = 0.0;
+  for (int a = 0; a < ORC_MMAX; ++a) l[a] = 0.0;
   if (lam0)
     memcpy(l, lam0, sizeof(double) * M);
   else
@@ -245,7 +305,7 @@ int orc_equilibrium_m(int M, double ux, double uy, double T, const double* lam0,
       if (t < 1e-12) return ORC_ERR_NEWTON;
     }
     memcpy(l, lt, sizeof l);
-    memcpy(w, wt, sizeof wt);
+    memcpy(w, wt, sizeof(double) * orc_lattice_of(M));
     memcpy(G, Gt, sizeof Gt);
     psi = psit;
   }
@@ -257,8 +317,12 @@ int orc_equilibrium(double ux, double uy, double T, const double* lam0,
   return orc_equilibrium_m(8, ux, uy, T, lam0, tol, max_iter, w, lam, iters);
 }
 
-/* Constraint count of a simulation: 8 (eq. 8moments) unless set to 4. */
-static int constraints_of(const orc_params* p) { return p->constraints == 4 ? 4 : 8; }
+/* Constraint count of a simulation: 8 (eq. 8moments) unless set to 4 or 13;
+ * its lattice follows (D2Q49 for 13, else D2Q21). */
+static int constraints_of(const orc_params* p) {
+  return p->constraints == 4 || p->constraints == 13 ? p->constraints : 8;
+}
+static int lattice_of(const orc_params* p) { return orc_lattice_of(constraints_of(p)); }
 
 /* ------------------------------------------------------ Grad populations
  * Eqs. (GradGeneral), (GradGeneral_f), (GradGeneral_g):
@@ -278,8 +342,9 @@ static void grad_phi(const orc_params* p, int i, double rho, double ux, double u
                      double T, const double* du, const double* dT, int Lx, int Ly,
                      double* phif, double* phig) {
   double Cv = 1.0 / (p->gamma - 1.0), Cp = p->gamma * Cv;
-  double cbx = (double)(XI[i][0] + Lx) - ux;
-  double cby = (double)(XI[i][1] + Ly) - uy;
+  const int Q = lattice_of(p);
+  double cbx = (double)(cx_of(Q, i) + Lx) - ux;
+  double cby = (double)(cy_of(Q, i) + Ly) - uy;
   double mu = rho * p->nu;
   double div = du[0] + du[3];
   double sxx = -mu * (2.0 * du[0] - (2.0 / ORC_D) * div);
@@ -297,15 +362,16 @@ static void grad_phi(const orc_params* p, int i, double rho, double ux, double u
 int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
                          double T, const double* du, const double* dT, int Lx,
                          int Ly, int post, double* f, double* g) {
-  double w[ORC_Q], lam[ORC_M];
+  double w[ORC_QMAX], lam[ORC_MMAX];
   double Cv = 1.0 / (p->gamma - 1.0);
+  const int Q = lattice_of(p);
   if (!(rho > 0.0) || !isfinite(rho)) return ORC_ERR_NONPHYSICAL;
   int rc = orc_equilibrium_m(constraints_of(p), ux - Lx, uy - Ly, T, NULL, p->newton_tol,
                              p->newton_max_iter, w, lam, NULL);
   if (rc) return rc;
   double tau = 0.5 + p->nu / T;
   double k = post ? (1.0 - 1.0 / tau) : 1.0;
-  for (int i = 0; i < ORC_Q; ++i) {
+  for (int i = 0; i < Q; ++i) {
     double phif, phig;
     grad_phi(p, i, rho, ux, uy, T, du, dT, Lx, Ly, &phif, &phig);
     double feq = rho * w[i];
@@ -320,6 +386,7 @@ int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
 struct orc_sim {
   orc_params p;
   long N;
+  int Q;                 /* velocities of the lattice */
   double *f, *g;         /* post-collision populations at time t */
   double *fp, *gp;       /* streamed (pre-collision) populations at t+1 */
   double *mac, *mac1;    /* rho, ux, uy, T per node */
@@ -396,7 +463,8 @@ static void select_neighbourhood(const orc_sim* s, long n, double ux, double uy,
 orc_sim* orc_create(const orc_params* p) {
   if (!p || p->nx < 1 || p->ny < 1 || !(p->gamma > 1.0) || !(p->nu >= 0.0) ||
       p->newton_max_iter < 1 || !(p->halfwidth >= 0.5) ||
-      (p->constraints != 0 && p->constraints != 4 && p->constraints != 8) ||
+      (p->constraints != 0 && p->constraints != 4 && p->constraints != 8 &&
+       p->constraints != 13) ||
       p->shift_mode < 0 || p->shift_mode > 3 ||
       (p->shift_mode == 3 && !(p->halfwidth < 1.0)))
     return NULL;
@@ -404,11 +472,13 @@ orc_sim* orc_create(const orc_params* p) {
   if (!s) return NULL;
   s->p = *p;
   s->N = (long)p->nx * p->ny;
+  s->Q = lattice_of(p);
   long N = s->N;
-  s->f = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
-  s->g = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
-  s->fp = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
-  s->gp = (double*)calloc((size_t)ORC_Q * N, sizeof(double));
+  size_t QN = (size_t)s->Q * N;
+  s->f = (double*)calloc(QN, sizeof(double));
+  s->g = (double*)calloc(QN, sizeof(double));
+  s->fp = (double*)calloc(QN, sizeof(double));
+  s->gp = (double*)calloc(QN, sizeof(double));
   s->mac = (double*)calloc((size_t)4 * N, sizeof(double));
   s->mac1 = (double*)calloc((size_t)4 * N, sizeof(double));
   s->Uc = (int*)calloc((size_t)2 * N, sizeof(int));
@@ -449,13 +519,13 @@ static void record_failure(orc_sim* s, long n, int rc, int* err) {
  * threshold 0.01 above which dissipation is added but not alpha itself.
  * Reading: alpha is piecewise constant, 1 below 1e-2, then 1.05, 1.35 and
  * 2 from 1e-1 and 1 upwards. */
-static double sensor_alpha(const double* f, double rho, const double* w) {
+static double sensor_alpha(int Q, const double* f, double rho, const double* w) {
   double eps = 0.0;
-  for (int i = 0; i < ORC_Q; ++i) {
+  for (int i = 0; i < Q; ++i) {
     double feq = rho * w[i];
     eps += fabs(f[i] - feq) / feq;
   }
-  eps /= ORC_Q;
+  eps /= Q;
   if (eps < 1e-2) return 1.0;
   if (eps < 1e-1) return 1.05;
   if (eps < 1.0) return 1.35;
@@ -469,6 +539,7 @@ static int collide_all(orc_sim* s) {
   const orc_params* p = &s->p;
   const long N = s->N;
   const double Cv = 1.0 / (p->gamma - 1.0);
+  const int Q = s->Q;
   int err = 0;
   long calls = 0, iters = 0;
   long hist[ORC_HIST];
@@ -476,18 +547,19 @@ static int collide_all(orc_sim* s) {
 #pragma omp parallel for schedule(static) reduction(+ : calls, iters)
   for (long n = 0; n < N; ++n) {
     const int Ux = s->Un[2 * n], Uy = s->Un[2 * n + 1];
-    double f[ORC_Q], g[ORC_Q];
-    for (int i = 0; i < ORC_Q; ++i) {
+    double f[ORC_QMAX], g[ORC_QMAX];
+    for (int i = 0; i < Q; ++i) {
       f[i] = s->fp[i * N + n];
       g[i] = s->gp[i * N + n];
     }
     /* moments in the frame of the lattice, eq. (polyTemp) */
     double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
-    for (int i = 0; i < ORC_Q; ++i) {
+    for (int i = 0; i < Q; ++i) {
+      const int x = cx_of(Q, i), y = cy_of(Q, i);
       rho += f[i];
-      jx += f[i] * XI[i][0];
-      jy += f[i] * XI[i][1];
-      e += (double)(XI[i][0] * XI[i][0] + XI[i][1] * XI[i][1]) * f[i] + g[i];
+      jx += f[i] * x;
+      jy += f[i] * y;
+      e += (double)(x * x + y * y) * f[i] + g[i];
     }
     double upx = jx / rho, upy = jy / rho;
     double T = (e - rho * (upx * upx + upy * upy)) / (2.0 * rho * Cv);
@@ -516,7 +588,7 @@ static int collide_all(orc_sim* s) {
       continue;
     }
     /* numerical equilibrium in the current lattice, eqs. (feqNum_8Mom), (gEq) */
-    double w[ORC_Q], lam[ORC_M];
+    double w[ORC_QMAX], lam[ORC_MMAX];
     int it = 0;
     int rc = orc_equilibrium_m(constraints_of(p), upx, upy, T, NULL, p->newton_tol,
                                p->newton_max_iter, w, lam, &it);
@@ -530,8 +602,8 @@ static int collide_all(orc_sim* s) {
     hist[it < ORC_HIST ? it : ORC_HIST - 1] += 1;
     /* BGK collision, eq. (coll), tau = 1/2 + nu / T (App. E) */
     double tau = 0.5 + p->nu / T;
-    if (p->sensor) tau *= sensor_alpha(f, rho, w);
-    for (int i = 0; i < ORC_Q; ++i) {
+    if (p->sensor) tau *= sensor_alpha(Q, f, rho, w);
+    for (int i = 0; i < Q; ++i) {
       double feq = rho * w[i];
       double geq = (2.0 * Cv - ORC_D) * T * feq;
       s->f[i * N + n] = f[i] - (f[i] - feq) / tau;
@@ -578,7 +650,7 @@ static void gradients(const orc_sim* s, const double* v, long n, double du[4],
  * the lattice of the receiving node. */
 static int reconstruct(const orc_sim* s, long src, int Lx, int Ly, int i, double* fi,
                        double* gi) {
-  double du[4], dT[2], f[ORC_Q], g[ORC_Q];
+  double du[4], dT[2], f[ORC_QMAX], g[ORC_QMAX];
   const double* m = s->mac + 4 * src;
   gradients(s, s->mac, src, du, dT);
   int rc = orc_grad_populations(&s->p, m[0], m[1], m[2], m[3], du, dT, Lx, Ly, 1, f, g);
@@ -624,14 +696,14 @@ int orc_init(orc_sim* s, const double* rho, const double* ux, const double* uy,
       record_failure(s, n, ORC_ERR_NONPHYSICAL, &err);
       continue;
     }
-    double du[4], dT[2], f[ORC_Q], g[ORC_Q];
+    double du[4], dT[2], f[ORC_QMAX], g[ORC_QMAX];
     gradients(s, v, n, du, dT);
     int rc = orc_grad_populations(p, rho[n], ux[n], uy[n], T[n], du, dT, Ux, Uy, 0, f, g);
     if (rc) {
       record_failure(s, n, rc, &err);
       continue;
     }
-    for (int i = 0; i < ORC_Q; ++i) {
+    for (int i = 0; i < s->Q; ++i) {
       s->fp[i * N + n] = f[i];
       s->gp[i * N + n] = g[i];
     }
@@ -654,6 +726,7 @@ int orc_set_static_shift(orc_sim* s, const int* Ux, const int* Uy) {
 int orc_step(orc_sim* s, int nsteps) {
   const long N = s->N;
   const long nx = s->p.nx, ny = s->p.ny;
+  const int Q = s->Q;
   for (int k = 0; k < nsteps; ++k) {
     int err = 0;
     long mism = 0;
@@ -664,9 +737,9 @@ int orc_step(orc_sim* s, int nsteps) {
     for (long n = 0; n < N; ++n) {
       const long x = n % nx, y = n / nx;
       const int Ux = s->Un[2 * n], Uy = s->Un[2 * n + 1];
-      for (int i = 0; i < ORC_Q; ++i) {
-        long sx = wrap(x - (XI[i][0] + Ux), nx);
-        long sy = wrap(y - (XI[i][1] + Uy), ny);
+      for (int i = 0; i < Q; ++i) {
+        long sx = wrap(x - (cx_of(Q, i) + Ux), nx);
+        long sy = wrap(y - (cy_of(Q, i) + Uy), ny);
         long src = sy * nx + sx;
         if (s->Uc[2 * src] == Ux && s->Uc[2 * src + 1] == Uy) {
           s->fp[i * N + n] = s->f[i * N + src];
@@ -702,7 +775,7 @@ void orc_macros(const orc_sim* s, double* rho, double* ux, double* uy, double* T
 }
 
 void orc_populations(const orc_sim* s, double* f, double* g) {
-  size_t bytes = sizeof(double) * ORC_Q * (size_t)s->N;
+  size_t bytes = sizeof(double) * s->Q * (size_t)s->N;
   if (f) memcpy(f, s->f, bytes);
   if (g) memcpy(g, s->g, bytes);
 }
@@ -711,9 +784,9 @@ void orc_conserved(const orc_sim* s, double* out4) {
   long double m = 0, px = 0, py = 0, en = 0;
   const long N = s->N;
   for (long n = 0; n < N; ++n) {
-    for (int i = 0; i < ORC_Q; ++i) {
+    for (int i = 0; i < s->Q; ++i) {
       long double f = s->f[i * N + n], g = s->g[i * N + n];
-      long double cx = XI[i][0] + s->Uc[2 * n], cy = XI[i][1] + s->Uc[2 * n + 1];
+      long double cx = cx_of(s->Q, i) + s->Uc[2 * n], cy = cy_of(s->Q, i) + s->Uc[2 * n + 1];
       m += f;
       px += f * cx;
       py += f * cy;

@@ -3,7 +3,8 @@
  * compressible lattice Boltzmann method of Coreixas & Latt (arXiv 2009.13426):
  * D2Q21 lattice, 8-constraint numerical (maximum-entropy) equilibrium,
  * double-distribution BGK collision, on-grid pull streaming with Grad
- * reconstruction where neighbouring lattice shifts differ.
+ * reconstruction where neighbouring lattice shifts differ; and the paper's
+ * reference model on the same framework, D2Q49 with 13 constraints (App. C).
  *
  * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
  * reference the GPU implementation is checked against.  Only the test suite,
@@ -12,7 +13,8 @@
  *
  * Conventions
  *  - Grid nx * ny, periodic in x and y; node n = y * nx + x.
- *  - Populations are stored SoA: h[i * N + n], i in [0, 21).
+ *  - Populations are stored SoA: h[i * N + n], i in [0, Q), Q = 21 (or 49
+ *    for the 13-constraint model).
  *  - Fields passed in or out are float64 arrays of N values, row-major [ny][nx].
  *  - All arithmetic is IEEE double, built with -ffp-contract=off.
  */
@@ -24,7 +26,10 @@ extern "C" {
 #endif
 
 #define ORC_Q 21          /* discrete velocities of D2Q21 */
+#define ORC_Q49 49        /* discrete velocities of D2Q49 */
+#define ORC_QMAX 49
 #define ORC_M 8           /* constraints of the 8-moment equilibrium */
+#define ORC_MMAX 13
 #define ORC_D 2           /* physical dimensions */
 #define ORC_HIST 128      /* Newton-iteration histogram bins */
 
@@ -50,7 +55,8 @@ typedef struct {
   int max_abs_shift;     /* |U_alpha| above this is reported as non-physical */
   int sensor;            /* 1: Knudsen sensor scales tau by alpha(eps_Kn) */
   int constraints;       /* 8 (or 0): eq. (8moments); 4: mass, momentum and energy
-                            only, eq. (feqNum_4Mom) */
+                            only, eq. (feqNum_4Mom); 13: eqs. (G0)-(G4yyaa) on the
+                            D2Q49 lattice (the paper's reference model) */
 } orc_params;
 
 typedef struct {
@@ -66,6 +72,10 @@ typedef struct orc_sim orc_sim;
 
 /* Velocity table: writes 21 integer components each. */
 void orc_velocities(int* cx, int* cy);
+/* Velocities of lattice Q (21 or 49); orc_lattice_of(M) is the lattice a
+ * constraint count is solved on (49 for M = 13, else 21). */
+void orc_velocities_q(int Q, int* cx, int* cy);
+int orc_lattice_of(int M);
 
 /* Numerical equilibrium per unit density in the frame of the lattice:
  * minimises sum_i w_i ln(w_i) under the 8 moment constraints for peculiar
@@ -78,9 +88,11 @@ int orc_equilibrium(double ux, double uy, double T, const double* lam0,
 /* Exact targets m[8] of the 8 constraints per unit density. */
 void orc_targets(double ux, double uy, double T, double* m);
 
-/* As orc_equilibrium / orc_targets for M = 8 or M = 4 constraints (M = 4:
- * phi = (1, xi_x, xi_y, |xi|^2), targets (1, u_x, u_y, 2E)); lam and m hold
- * M values.  ORC_ERR_ARG for another M. */
+/* As orc_equilibrium / orc_targets for M = 8, 4 or 13 constraints (M = 4:
+ * phi = (1, xi_x, xi_y, |xi|^2), targets (1, u_x, u_y, 2E); M = 13: the
+ * monomials up to third order and the contracted fourth-order ones on
+ * D2Q49, w then holds 49 weights); lam and m hold M values.  ORC_ERR_ARG for
+ * another M. */
 int orc_equilibrium_m(int M, double ux, double uy, double T, const double* lam0,
                       double tol, int max_iter, double* w, double* lam, int* iters);
 void orc_targets_m(int M, double ux, double uy, double T, double* m);
@@ -88,7 +100,7 @@ void orc_targets_m(int M, double ux, double uy, double T, double* m);
 /* Grad populations h = h_eq (1 + phi) for lattice shift (Lx, Ly) at a state
  * with gradients du = (dux/dx, dux/dy, duy/dx, duy/dy), dT = (dT/dx, dT/dy).
  * post != 0 returns post-collision h_eq (1 + (1 - 1/tau) phi) instead.
- * Writes f[21], g[21]. */
+ * Writes f[Q], g[Q] (Q of the constraint set in p). */
 int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
                          double T, const double* du, const double* dT, int Lx,
                          int Ly, int post, double* f, double* g);
