@@ -87,7 +87,13 @@ typedef struct {
   int32_t constraints;       /* moment constraints of the numerical equilibrium:
                                 8 = eq. (8moments) (default); 4 = mass, momentum and
                                 energy only, eq. (feqNum_4Mom), Sec. "Reduced models"
-                                (4 x 4 solve; runs the default schedule only) */
+                                (4 x 4 solve; runs the default schedule only);
+                                13 = the paper's reference model (App. C, eqs.
+                                (G0)-(G4yyaa)): the D2Q49 lattice {-3..3}^2 with all
+                                moments up to third order and the contracted
+                                fourth-order ones, 13 x 13 solve from the lattice
+                                Maxwellian.  FP64 only, shift modes 0-2, default
+                                schedule, not in lbm_step_batched */
 } lbm_config;
 
 typedef struct {
@@ -209,12 +215,19 @@ lbm_status lbm_sync(lbm_ctx* ctx);
 lbm_status lbm_get_macros(lbm_ctx* ctx, double* rho, double* ux, double* uy,
                           double* T, int8_t* Ux, int8_t* Uy);
 
-/* Post-collision populations as device float64 [21][ny][nx] each (FP32
- * storage is widened), in the velocity order of lbm_velocities.  Synchronous. */
+/* Post-collision populations as device float64 [Q][ny][nx] each, Q = 21
+ * (or 49 with 13 constraints; FP32 storage is widened), in the velocity
+ * order of lbm_lattice_velocities.  Synchronous. */
 lbm_status lbm_get_populations(lbm_ctx* ctx, double* f, double* g);
 
 /* Host arrays of 21 ints: the velocity set in storage order. */
 void lbm_velocities(int32_t* cx, int32_t* cy);
+
+/* The storage-order velocity set of a constraint count's lattice (Sec. I;
+ * App. C for D2Q49: velocity k = (k mod 7 - 3, k div 7 - 3)) into host
+ * arrays of up to 49 ints (nullable); returns the number of velocities, 21
+ * or 49, or 0 for a constraint count the library does not build. */
+int32_t lbm_lattice_velocities(int32_t constraints, int32_t* cx, int32_t* cy);
 
 /* Counters, error record and conserved sums (computed on the device in a
  * fixed summation order).  out: host pointer.  Synchronous. */

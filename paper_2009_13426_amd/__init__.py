@@ -37,11 +37,15 @@ def _check(status: int, where: str):
         raise LBMError(status, where)
 
 
-def velocities():
-    cx = (C.c_int32 * Q)()
-    cy = (C.c_int32 * Q)()
-    lib.lbm_velocities(cx, cy)
-    return list(zip(cx, cy))
+def velocities(constraints=8):
+    """Velocity set in storage order of a constraint count's lattice: D2Q21,
+    or D2Q49 for the 13-constraint reference model."""
+    cx = (C.c_int32 * 49)()
+    cy = (C.c_int32 * 49)()
+    q = lib.lbm_lattice_velocities(int(constraints), cx, cy)
+    if q == 0:
+        raise ValueError(f"no lattice for {constraints} constraints")
+    return list(zip(cx[:q], cy[:q]))
 
 
 def make_config(nx: int, ny: int, precision="fp64", gamma=1.4, nu=0.0, shift_mode="adaptive",
@@ -75,14 +79,15 @@ class Sim:
                  **kw):
         """schedule: None (library default), a dict of lbm_schedule fields,
         or "auto" (the autotuner's cached choice for this size class,
-        tuned on a miss; the library default for the four-constraint set
-        and the neighbourhood shift choice, which are built for that
-        schedule only)."""
+        tuned on a miss; the library default for the four- and
+        13-constraint sets and the neighbourhood shift choice, which are
+        built for that schedule only)."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
         self.cfg = make_config(nx, ny, **kw)
         self.nx, self.ny = int(nx), int(ny)
+        self.Q = 49 if self.cfg.constraints == 13 else Q
         nbytes = workspace_bytes(self.cfg)
         if nbytes == 0:
             raise ValueError(f"invalid configuration {kw} for {nx}x{ny}")
@@ -202,7 +207,7 @@ class Sim:
 
     def populations(self):
         t = self.torch
-        f = t.empty((Q, self.ny, self.nx), dtype=t.float64, device=self.device)
+        f = t.empty((self.Q, self.ny, self.nx), dtype=t.float64, device=self.device)
         g = t.empty_like(f)
         _check(lib.lbm_get_populations(self._ctx, C.c_void_p(f.data_ptr()),
                                        C.c_void_p(g.data_ptr())), "lbm_get_populations")

@@ -56,6 +56,8 @@ SIGNATURES = {
     "lbm_get_macros": (C.c_int, [C.c_void_p] + [C.c_void_p] * 6),
     "lbm_get_populations": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lbm_velocities": (None, [C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "lbm_lattice_velocities": (C.c_int32, [C.c_int32, C.POINTER(C.c_int32),
+                                           C.POINTER(C.c_int32)]),
     "lbm_get_diag": (C.c_int, [C.c_void_p, C.POINTER(Diag)]),
     "lbm_step_batched": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_int32), C.c_int32]),
     "lbm_destroy": (None, [C.c_void_p]),

@@ -12,7 +12,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = [os.path.join(CSRC, "lbm.hip")]
-HEADERS = [os.path.join(CSRC, h) for h in ("kernels.hpp", "equilibrium.hpp", "lattice.hpp")] + \
+HEADERS = [os.path.join(CSRC, h) for h in ("kernels.hpp", "equilibrium.hpp", "equilibrium4.hpp",
+                                           "equilibrium13.hpp", "reference49.hpp",
+                                           "lattice.hpp")] + \
     [os.path.join(ROOT, "include", "lbm.h")]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,293 @@
+// Numerical equilibrium of the paper's reference model (App. C): the D2Q49
+// lattice {-3, ..., 3}^2 with 13 constraints, eqs. (G0)-(G4yyaa), solved per
+// lane in FP64 registers:
+//
+//   w_i = exp(-l . phi(xi_i)),  sum_i w_i phi(xi_i) = m(u', T),
+//   phi = (1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3,
+//          x^2 |xi|^2, xy |xi|^2, y^2 |xi|^2)
+//
+// in the frame of the lattice (peculiar velocity u' = u - U; every monomial
+// of degree <= 3 is in the span, so the span is invariant under integer
+// translations).  l[0] includes the 1 of the exponent.  The printed
+// exponent of eq. (feqNum_13Mom) lists no multiplier for x^3 although G_3,xxx
+// is a constraint; it is taken as a dropped term (13 multipliers).
+//
+// Newton on G(l) = sum_i w_i phi_i - m with H = sum_i w_i phi_i phi_i^T, the
+// Hessian of the strictly convex dual Psi(l) = sum_i w_i(l) + l . m, from
+// the lattice Maxwellian, steps halved until Psi decreases (a full step is
+// also taken when it halves the residual); stop at max_a |G_a| <= tol, then
+// one more step so that the constraints hold to rounding.
+//
+// G and H need only the 45 power moments mu(p, q) = sum_i w_i x^p y^q,
+// p + q <= 8; they are taken row by row, the rows and columns of the
+// lattice folded by their +- symmetry (odd powers from differences, even
+// powers from sums).
+#pragma once
+
+#include "equilibrium.hpp"
+
+namespace lbm {
+
+constexpr int kQ49 = 49;
+constexpr int kM13 = 13;
+constexpr int kTri13 = kM13 * (kM13 + 1) / 2;
+
+// Storage plane k of D2Q49: velocity (k mod 7 - 3, k div 7 - 3).
+__host__ __device__ constexpr int cx49(int k) { return k % 7 - 3; }
+__host__ __device__ constexpr int cy49(int k) { return k / 7 - 3; }
+
+// Monomial a as a sum of one or two terms x^p y^q.
+constexpr int kNT13[kM13] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2};
+constexpr int kTP13[kM13][2] = {{0, 0}, {1, 0}, {0, 0}, {2, 0}, {1, 0}, {0, 0}, {3, 0},
+                                {2, 0}, {1, 0}, {0, 0}, {4, 2}, {3, 1}, {2, 0}};
+constexpr int kTQ13[kM13][2] = {{0, 0}, {0, 0}, {1, 0}, {0, 0}, {1, 0}, {2, 0}, {0, 0},
+                                {1, 0}, {2, 0}, {3, 0}, {0, 2}, {1, 3}, {2, 4}};
+
+__host__ __device__ constexpr int phi13(int a, int x, int y) {
+  int v = 0;
+  for (int t = 0; t < kNT13[a]; ++t) v += ipow(x, kTP13[a][t]) * ipow(y, kTQ13[a][t]);
+  return v;
+}
+
+// Exponent l . phi(x, y) of velocity (x, y), coefficients folded in.
+template <int X, int Y>
+__device__ __forceinline__ double exponent13(const double (&l)[kM13]) {
+  double e = l[0];
+  static_for<1, kM13>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    e = cmad<phi13(a, X, Y)>(e, l[a]);
+  });
+  return e;
+}
+
+// Weight of plane k for multipliers l.
+template <int K>
+__device__ __forceinline__ double weight13(const double (&l)[kM13]) {
+  return exp_cw(-exponent13<cx49(K), cy49(K)>(l));
+}
+
+// Power moments mu[p][q], p + q <= 8, of the weights of l; returns
+// mu[0][0] = sum_i w_i.
+__device__ __forceinline__ void power_moments13(const double (&l)[kM13], double (&mu)[9][9]) {
+  static_for<0, 9>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    static_for<0, 9 - p>([&](auto qc) { mu[p][decltype(qc)::value] = 0.0; });
+  });
+  // r[p] = sum_x x^p w(x, y) of row y, for the rows y and -y together
+  static_for<0, 4>([&](auto yc) {
+    constexpr int y = decltype(yc)::value;
+    double rp[9], rm[9];
+    static_for<0, (y == 0 ? 1 : 2)>([&](auto sc) {
+      constexpr int yy = decltype(sc)::value == 0 ? y : -y;
+      double r[9];
+      const double w0 = exp_cw(-exponent13<0, yy>(l));
+      double S[4], D[4];
+      static_for<1, 4>([&](auto xc) {
+        constexpr int x = decltype(xc)::value;
+        const double wp = exp_cw(-exponent13<x, yy>(l));
+        const double wm = exp_cw(-exponent13<-x, yy>(l));
+        S[x] = wp + wm;
+        D[x] = wp - wm;
+      });
+      static_for<0, 9>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        double acc = p == 0 ? w0 : 0.0;
+        static_for<1, 4>([&](auto xc) {
+          constexpr int x = decltype(xc)::value;
+          acc = cmad<ipow(x, p)>(acc, (p & 1) ? D[x] : S[x]);
+        });
+        r[p] = acc;
+      });
+      static_for<0, 9>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        if constexpr (decltype(sc)::value == 0)
+          rp[p] = r[p];
+        else
+          rm[p] = r[p];
+      });
+    });
+    static_for<0, 9>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      if constexpr (y == 0) {
+        mu[p][0] += rp[p];
+      } else {
+        const double s = rp[p] + rm[p], d = rp[p] - rm[p];
+        static_for<0, 9 - p>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          mu[p][q] = cmad<ipow(y, q)>(mu[p][q], (q & 1) ? d : s);
+        });
+      }
+    });
+  });
+}
+
+// Targets per unit density, eqs. (G0)-(G4yyaa), 2E = |u'|^2 + D T, D = 2.
+__device__ __forceinline__ void targets13(double ux, double uy, double T, double (&m)[kM13]) {
+  const double E = 0.5 * (ux * ux + uy * uy + 2.0 * T);
+  m[0] = 1.0;
+  m[1] = ux;
+  m[2] = uy;
+  m[3] = ux * ux + T;
+  m[4] = ux * uy;
+  m[5] = uy * uy + T;
+  m[6] = ux * (ux * ux + 3.0 * T);
+  m[7] = (ux * ux + T) * uy;
+  m[8] = ux * (uy * uy + T);
+  m[9] = uy * (uy * uy + 3.0 * T);
+  m[10] = 2.0 * ((E + 2.0 * T) * ux * ux + (E + T) * T);
+  m[11] = 2.0 * (E + 2.0 * T) * ux * uy;
+  m[12] = 2.0 * ((E + 2.0 * T) * uy * uy + (E + T) * T);
+}
+
+__host__ __device__ constexpr int tri13(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// G_a = sum of mu over the terms of monomial a, minus m_a; lower triangle
+// of H from the products of terms.
+__device__ __forceinline__ void residual13(const double (&mu)[9][9], const double (&m)[kM13],
+                                           double (&G)[kM13]) {
+  static_for<0, kM13>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    double g = mu[kTP13[a][0]][kTQ13[a][0]];
+    if constexpr (kNT13[a] == 2) g += mu[kTP13[a][1]][kTQ13[a][1]];
+    G[a] = g - m[a];
+  });
+}
+
+__device__ __forceinline__ void hessian13(const double (&mu)[9][9], double (&H)[kTri13]) {
+  static_for<0, kM13>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    static_for<0, a + 1>([&](auto bc) {
+      constexpr int b = decltype(bc)::value;
+      double h = 0.0;
+      static_for<0, kNT13[a]>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        static_for<0, kNT13[b]>([&](auto tc) {
+          constexpr int t = decltype(tc)::value;
+          h += mu[kTP13[a][s] + kTP13[b][t]][kTQ13[a][s] + kTQ13[b][t]];
+        });
+      });
+      H[tri13(a, b)] = h;
+    });
+  });
+}
+
+// Solves H d = G by an in-place LDL^T of the symmetric positive definite
+// 13 x 13 matrix (lower triangle, row-major); false on a non-positive pivot.
+__device__ __forceinline__ bool solve13(double (&A)[kTri13], const double (&G)[kM13],
+                                        double (&d)[kM13]) {
+  double inv[kM13];
+#pragma unroll
+  for (int j = 0; j < kM13; ++j) {
+    // A(j, k) for k < j holds L(j, k) D(k); turn row j into L and D
+#pragma unroll
+    for (int k = 0; k < j; ++k) {
+      const double ljk = A[tri13(j, k)] * inv[k];
+      A[tri13(j, j)] -= ljk * A[tri13(j, k)];
+#pragma unroll
+      for (int i = j + 1; i < kM13; ++i) A[tri13(i, j)] -= A[tri13(i, k)] * ljk;
+      A[tri13(j, k)] = ljk;
+    }
+    const double dj = A[tri13(j, j)];
+    if (!(dj > 0.0)) return false;
+    inv[j] = rcp64(dj);
+  }
+  double y[kM13];
+#pragma unroll
+  for (int i = 0; i < kM13; ++i) {
+    double v = G[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= A[tri13(i, k)] * y[k];
+    y[i] = v;
+  }
+#pragma unroll
+  for (int i = kM13 - 1; i >= 0; --i) {
+    double v = y[i] * inv[i];
+#pragma unroll
+    for (int k = i + 1; k < kM13; ++k) v -= A[tri13(k, i)] * d[k];
+    d[i] = v;
+  }
+  return true;
+}
+
+// Multipliers of the equilibrium at (u', T); the weights follow from
+// weight13<k>(l).
+__device__ __forceinline__ NewtonOut solve_equilibrium13(double ux, double uy, double T,
+                                                         double tol, int max_iter,
+                                                         double (&l)[kM13]) {
+  NewtonOut out{0, false};
+  if (!(T > 0.0) || !(T < 1e300) || !(fabs(ux) < 1e300) || !(fabs(uy) < 1e300)) return out;
+  double m[kM13];
+  targets13(ux, uy, T, m);
+  double mu[9][9];
+  {
+    const double iT = rcp64(T);
+#pragma unroll
+    for (int a = 0; a < kM13; ++a) l[a] = 0.0;
+    l[1] = -ux * iT;
+    l[2] = -uy * iT;
+    l[3] = 0.5 * iT;
+    l[5] = 0.5 * iT;
+    power_moments13(l, mu);
+    const double z = mu[0][0];
+    if (!(z > 1e-300) || !(z < 1e300)) return out;
+    l[0] = log(z);  // sum_i w_i = 1
+  }
+  power_moments13(l, mu);
+  double psi = mu[0][0];
+#pragma unroll
+  for (int a = 0; a < kM13; ++a) psi += l[a] * m[a];
+  for (int it = 0; it < max_iter; ++it) {
+    double G[kM13], H[kTri13], d[kM13];
+    residual13(mu, m, G);
+    hessian13(mu, H);
+    double r = 0.0;
+#pragma unroll
+    for (int a = 0; a < kM13; ++a) r = fmax(r, fabs(G[a]));
+    out.iters = it + 1;
+    if (!(r < 1e300) || !(psi < 1e300)) return out;
+    if (!solve13(H, G, d)) return out;
+    if (r <= tol) {
+#pragma unroll
+      for (int a = 0; a < kM13; ++a) l[a] += d[a];
+      out.ok = true;
+      return out;
+    }
+    // the dual decreases along d at rate -G . d < 0
+    double slope = 0.0;
+#pragma unroll
+    for (int a = 0; a < kM13; ++a) slope -= G[a] * d[a];
+    double t = 1.0;
+    bool moved = false;
+    for (int k = 0; k < 60; ++k) {
+      double lt[kM13];
+#pragma unroll
+      for (int a = 0; a < kM13; ++a) lt[a] = __builtin_fma(t, d[a], l[a]);
+      power_moments13(lt, mu);
+      double pt = mu[0][0];
+#pragma unroll
+      for (int a = 0; a < kM13; ++a) pt += lt[a] * m[a];
+      bool accept = pt <= psi + 1e-4 * t * slope;
+      if (!accept && t == 1.0 && pt < 1e300) {
+        double Gt[kM13];
+        residual13(mu, m, Gt);
+        double rt = 0.0;
+#pragma unroll
+        for (int a = 0; a < kM13; ++a) rt = fmax(rt, fabs(Gt[a]));
+        accept = rt < 0.5 * r;
+      }
+      if (accept) {
+#pragma unroll
+        for (int a = 0; a < kM13; ++a) l[a] = lt[a];
+        psi = pt;
+        moved = true;
+        break;
+      }
+      t *= 0.5;
+    }
+    if (!moved) return out;
+    // mu now holds the moments of the accepted point
+  }
+  return out;
+}
+
+}  // namespace lbm

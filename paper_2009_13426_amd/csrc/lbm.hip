@@ -1,7 +1,8 @@
-// Host runtime and C ABI (include/lbm.h) of the adaptive D2Q21 step.
+// Host runtime and C ABI (include/lbm.h) of the adaptive D2Q21 step (and of
+// the reference model, D2Q49 with 13 constraints, on the same framework).
 //
 // A context owns no device memory: it carves the caller's workspace into two
-// population buffers (A/B, 42 planes each), two lattice-tag arrays, the
+// population buffers (A/B, 2 x 21 or 2 x 49 planes each), two lattice-tag arrays, the
 // diagnostics record and the reduction partials, and enqueues every kernel
 // on the caller's stream.
 #include <hip/hip_runtime.h>
@@ -16,6 +17,7 @@
 
 #include "kernels.hpp"
 #include "lbm.h"
+#include "reference49.hpp"
 
 using namespace lbm;
 
@@ -35,8 +37,12 @@ constexpr float kTabSmax = 1.0f / 0.3f;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Velocities of a constraint set's lattice: D2Q49 for the 13-constraint
+// reference model, D2Q21 otherwise.
+int lattice_q(int constraints) { return constraints == kM13 ? kQ49 : kQ; }
+
 struct Layout {
-  size_t pop_bytes;  // one buffer: f and g, 21 planes each
+  size_t pop_bytes;  // one buffer: f and g, Q planes each
   size_t tag_bytes;
   size_t diag_off, part_off, sums_off, table_off, total;
   size_t off_pop[2], off_tag[2];
@@ -59,14 +65,17 @@ bool config_ok(const lbm_config* c) {
          c->shift_halfwidth < 8.0 && c->newton_tol > 0.0 && c->newton_max_iter >= 1 &&
          c->newton_max_iter <= 1000 && c->max_abs_shift >= 0 && c->max_abs_shift <= 12 &&
          std::abs(c->fixed_ux) <= c->max_abs_shift && std::abs(c->fixed_uy) <= c->max_abs_shift &&
-         (c->constraints == kM || c->constraints == 4);
+         (c->constraints == kM || c->constraints == 4 ||
+          (c->constraints == kM13 && c->precision == LBM_FP64 &&
+           c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD));
 }
 
 Layout layout(const lbm_config* c) {
   Layout L{};
   const size_t N = static_cast<size_t>(c->nx) * c->ny;
   const size_t es = c->precision == LBM_FP64 ? sizeof(double) : sizeof(float);
-  L.pop_bytes = align_up(2 * kQ * N * es);
+  const size_t Q = static_cast<size_t>(lattice_q(c->constraints));
+  L.pop_bytes = align_up(2 * Q * N * es);
   L.tag_bytes = align_up(N * sizeof(int));
   L.nparts = static_cast<int>((N + kBlock - 1) / kBlock);
   size_t off = 0;
@@ -80,8 +89,8 @@ Layout layout(const lbm_config* c) {
   }
   L.mac_off = off;
   off += align_up(4 * N * (LBM_CARRY_FP64 ? sizeof(double) : es));
-  L.mask_off = off;
-  off += align_up(N * sizeof(unsigned));
+  L.mask_off = off;  // one link bit per velocity
+  off += align_up(N * (Q > 32 ? sizeof(unsigned long long) : sizeof(unsigned)));
   L.list_off = off;
   off += align_up(N * sizeof(int));
   L.count_off = off;
@@ -153,7 +162,7 @@ struct lbm_ctx {
   void* f(int b) const { return ws + lay.off_pop[b]; }
   void* g(int b) const {
     const size_t es = cfg.precision == LBM_FP64 ? sizeof(double) : sizeof(float);
-    return ws + lay.off_pop[b] + kQ * static_cast<size_t>(grid.N) * es;
+    return ws + lay.off_pop[b] + lattice_q(cfg.constraints) * static_cast<size_t>(grid.N) * es;
   }
   int* tag(int b) const { return reinterpret_cast<int*>(ws + lay.off_tag[b]); }
   Carry carry() const {
@@ -200,6 +209,11 @@ const void* step_fn_of(bool tiled) {
 const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled, int M,
                            bool nbh = false) {
   const bool f64 = precision == LBM_FP64;
+  if (M == kM13) {  // reference model: FP64, 64-lane untiled blocks
+    if (!f64 || block != 64 || tiled || nbh) return nullptr;
+    return stream_pass ? reinterpret_cast<const void*>(&step49_kernel<true>)
+                       : reinterpret_cast<const void*>(&step49_kernel<false>);
+  }
   if (nbh) {  // shift mode 3: default schedule, 8 constraints
     if (block != 64 || tiled || M != kM) return nullptr;
     if (f64)
@@ -263,6 +277,7 @@ const void* step_batched_fn(int precision, int block, int M) {
 
 const void* rebuild_fn(int precision, int M) {
   const bool f64 = precision == LBM_FP64;
+  if (M == kM13) return f64 ? reinterpret_cast<const void*>(&rebuild49_kernel) : nullptr;
   if (M == 4)
     return f64 ? reinterpret_cast<const void*>(&rebuild_kernel<double, 4>)
                : reinterpret_cast<const void*>(&rebuild_kernel<float, 4>);
@@ -453,7 +468,9 @@ bool schedule_ok(const lbm_ctx* c, const lbm_schedule* s) {
   if (!step_kernel_fn(c->cfg.precision, true, s->step_block, tiled, c->cfg.constraints,
                       c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD))
     return false;
-  if (!step_batched_fn(c->cfg.precision, s->step_block, c->cfg.constraints)) return false;
+  if (c->cfg.constraints != kM13 &&
+      !step_batched_fn(c->cfg.precision, s->step_block, c->cfg.constraints))
+    return false;
   const long long tiles = (c->grid.N + s->step_block - 1) / s->step_block;
   return s->tiles_per_block >= 1 && s->tiles_per_block <= 64 && tiles < (1ll << 31) &&
          (s->xcd_remap == 0 || s->xcd_remap == 1) && s->rebuild_blocks >= 0 &&
@@ -490,7 +507,9 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
   a.phys = c->phys;
   a.table = c->table;
   a.diag = c->diag();
-  if (c->cfg.constraints == 4) {
+  if (c->cfg.constraints == kM13) {
+    hipLaunchKernelGGL(init49_kernel, dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
+  } else if (c->cfg.constraints == 4) {
     if (c->cfg.precision == LBM_FP64)
       hipLaunchKernelGGL((init_kernel<double, 4>), dim3(c->nblocks), dim3(kBlock), 0, c->stream, a);
     else
@@ -595,7 +614,9 @@ lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, s
   hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
                      c->carry().counters);
   const size_t table_bytes = static_cast<size_t>(kTabU) * kTabU * kTabS * 8 * sizeof(float);
-  if (like && like->cfg.constraints == cfg->constraints) {
+  if (cfg->constraints == kM13) {
+    // the reference model's solve starts from the lattice Maxwellian: no table
+  } else if (like && like->cfg.constraints == cfg->constraints) {
     if (hipMemcpyAsync(c->ws + L.table_off, like->ws + like->lay.table_off, table_bytes,
                        hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
       delete c;
@@ -784,7 +805,11 @@ lbm_status lbm_get_macros(lbm_ctx* c, double* rho, double* ux, double* uy, doubl
   if (!c || !rho || !ux || !uy || !T) return LBM_ERR_ARG;
   if (!c->initialized) return LBM_ERR_STATE;
   const int b = c->cur;
-  if (c->cfg.precision == LBM_FP64)
+  if (c->cfg.constraints == kM13)
+    hipLaunchKernelGGL(macros49_kernel, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                       static_cast<const double*>(c->f(b)), static_cast<const double*>(c->g(b)),
+                       c->tag(b), c->grid.N, c->phys.Cv, rho, ux, uy, T, Ux, Uy);
+  else if (c->cfg.precision == LBM_FP64)
     hipLaunchKernelGGL(macros_kernel<double>, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
                        static_cast<const double*>(c->f(b)), static_cast<const double*>(c->g(b)),
                        c->tag(b), c->grid.N, c->phys.Cv, rho, ux, uy, T, Ux, Uy);
@@ -801,7 +826,7 @@ lbm_status lbm_get_populations(lbm_ctx* c, double* f, double* g) {
   if (!c || !f || !g) return LBM_ERR_ARG;
   if (!c->initialized) return LBM_ERR_STATE;
   const int b = c->cur;
-  const long long cnt = kQ * c->grid.N;
+  const long long cnt = lattice_q(c->cfg.constraints) * c->grid.N;
   if (c->cfg.precision == LBM_FP64) {
     HIP_TRY(hipMemcpyAsync(f, c->f(b), cnt * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(g, c->g(b), cnt * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -824,6 +849,16 @@ void lbm_velocities(int32_t* cx, int32_t* cy) {
   }
 }
 
+int32_t lbm_lattice_velocities(int32_t constraints, int32_t* cx, int32_t* cy) {
+  if (constraints != kM && constraints != 4 && constraints != kM13) return 0;
+  const int Q = lattice_q(constraints);
+  for (int k = 0; k < Q; ++k) {
+    if (cx) cx[k] = Q == kQ49 ? cx49(k) : plane_cx(k);
+    if (cy) cy[k] = Q == kQ49 ? cy49(k) : plane_cy(k);
+  }
+  return Q;
+}
+
 lbm_status lbm_get_diag(lbm_ctx* c, lbm_diag* out) {
   if (!c || !out) return LBM_ERR_ARG;
   std::memset(out, 0, sizeof *out);
@@ -832,7 +867,11 @@ lbm_status lbm_get_diag(lbm_ctx* c, lbm_diag* out) {
   double sums[4] = {0, 0, 0, 0};
   if (c->initialized || c->steps_done == 0) {
     const int b = c->cur;
-    if (c->cfg.precision == LBM_FP64)
+    if (c->cfg.constraints == kM13)
+      hipLaunchKernelGGL(conserved49_kernel, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
+                         static_cast<const double*>(c->f(b)),
+                         static_cast<const double*>(c->g(b)), c->tag(b), c->grid.N, c->parts());
+    else if (c->cfg.precision == LBM_FP64)
       hipLaunchKernelGGL(conserved_kernel<double>, dim3(c->nblocks), dim3(kBlock), 0, c->stream,
                          static_cast<const double*>(c->f(b)),
                          static_cast<const double*>(c->g(b)), c->tag(b), c->grid.N, c->parts());
@@ -873,7 +912,8 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
   for (int32_t k = 0; k < n; ++k) {
     lbm_ctx* c = ctxs[k];
     if (!c || nsteps[k] < 0) return LBM_ERR_ARG;
-    if (c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD) return LBM_ERR_ARG;
+    if (c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD || c->cfg.constraints == kM13)
+      return LBM_ERR_ARG;
     if (c->cfg.precision != ctxs[0]->cfg.precision ||
         c->cfg.constraints != ctxs[0]->cfg.constraints || c->stream != ctxs[0]->stream ||
         c->device != ctxs[0]->device)

@@ -101,4 +101,14 @@ def test_size_limits_and_invalid_configs(so):
     assert size(8, 8, shift_mode=3, shift_halfwidth=0.9, constraints=4) == 0
     assert size(8, 8, constraints=5) == 0 and size(8, 8, constraints=4) > 0
     assert size(8, 8, newton_max_iter=0) == 0
+    # the 13-constraint reference model: D2Q49, FP64 only, no neighbourhood choice
+    assert size(8, 8, constraints=13) > 2 * 2 * 49 * 64 * 8
+    assert size(8, 8, constraints=13, precision=1) == 0
+    assert size(8, 8, constraints=13, shift_mode=3, shift_halfwidth=0.9) == 0
+    cx = (ctypes.c_int32 * 49)()
+    cy = (ctypes.c_int32 * 49)()
+    assert L.lbm_lattice_velocities(13, cx, cy) == 49
+    assert sorted(zip(cx, cy)) == [(a, b) for a in range(-3, 4) for b in range(-3, 4)]
+    assert L.lbm_lattice_velocities(8, cx, cy) == 21 and L.lbm_lattice_velocities(4, None, None) == 21
+    assert L.lbm_lattice_velocities(5, cx, cy) == 0
     assert size(8, 8, max_abs_shift=13) == 0
