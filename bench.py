@@ -51,7 +51,10 @@ def bytes_per_node(precision):
     """Algorithmic HBM bytes per node update of the step kernel: read and
     write 2 x 21 populations, read and write the node's lattice tag and its
     rebuilt-link mask (4 bytes each), write the four moments of the
-    collision that the next step's link rebuild reads."""
+    collision that the next step's link rebuild reads.  "ref49": the same
+    for the reference model (2 x 49 FP64 populations, 8-byte link mask)."""
+    if precision == "ref49":
+        return 2 * 2 * 49 * 8 + 2 * 4 + 2 * 8 + 4 * 8
     es = 8 if precision == "fp64" else 4
     return 2 * 2 * Q * es + 2 * 4 + 2 * 4 + 4 * es
 
@@ -189,7 +192,8 @@ def main():
                          "(cached; tuned before the timed region on a miss) or the library "
                          "default")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip timing the four-constraint equilibrium variant (FP32 storage)")
+                    help="skip timing the four-constraint equilibrium variant (FP32 storage) "
+                         "and the reference model (D2Q49, 13 constraints, FP64)")
     ap.add_argument("--graph-chunk", type=int, default=10,
                     help="steps per HIP graph replayed in the timed region (even)")
     ap.add_argument("--forms", default="fp32,fp64")
@@ -245,6 +249,18 @@ def main():
             equilibrium="mass, momentum and energy constraints only (4 x 4 solve)")
         print(f"[bench] fp32 four constraints: {v['mlups']:.1f} MLUPS", file=sys.stderr,
               flush=True)
+        # the reference model is about ten times slower per node: fewer steps
+        rsteps, rwarm = min(args.steps, 20), min(args.warmup, 4)
+        print(f"[bench] timing the reference model (D2Q49, 13 constraints, fp64), "
+              f"{rsteps} steps", file=sys.stderr, flush=True)
+        v = time_form(lbm, torch, wl, "fp64", rsteps, rwarm, None, 2, constraints=13)
+        variants["fp64_reference_d2q49_constraints13"] = dict(
+            mlups=round(v["mlups"], 2), kernel_ms=round(v["kernel_ms"], 4),
+            rebuild_ms=round(v["rebuild_ms"], 4), status=v["status"], steps=rsteps,
+            warmup=rwarm,
+            equilibrium="D2Q49 lattice, 13 constraints up to the contracted fourth-order "
+                        "moments (13 x 13 solve), FP64 storage")
+        print(f"[bench] reference model: {v['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
     head = "fp32" if "fp32" in res else next(iter(res))
     counters = {f: {} for f in res}
     if not args.no_counters:

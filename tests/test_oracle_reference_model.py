@@ -245,3 +245,26 @@ def test_only_paired_sets_are_accepted(orc):
     assert orc.equilibrium(0.1, 0.0, 0.7, constraints=12)[3] == orc.ERR_ARG
     with pytest.raises(ValueError):
         orc.Sim(4, 4, constraints=9)
+
+
+@pytest.mark.parametrize("gamma", [1.4, 5.0 / 3.0, 2.0])
+def test_printed_heat_flux_term_carries_momentum(orc, gamma):
+    """Reading D-6 as printed, on the lattice whose moments up to fourth
+    (contracted) order are exact: the heat-flux term of eq. (GradGeneral_f),
+    q.cbar / (rho Cp T^2) (|cbar|^2 / (2T) - Cp) f_eq, has first moment
+    (2 - Cp) / (Cp T) q, which vanishes only for Cp = (D + 2) / 2 = 2, the
+    translational (monatomic) value.  With the polyatomic Cp the term is not
+    momentum-free, so a collision that adds it at every node (the
+    flexible-Prandtl extension, eq. Shakhov) would not conserve momentum."""
+    nu, rho, T, dT = 0.05, 1.0, 0.7, 0.01
+    Cp = gamma / (gamma - 1.0)
+    p = orc.make_params(8, 8, nu=nu, gamma=gamma, constraints=13)
+    v = orc.velocities(49).astype(float)
+    f, g, rc = orc.grad_populations(p, rho, 0.0, 0.0, T, [0, 0, 0, 0], [dT, 0.0], (0, 0), 0)
+    assert rc == 0
+    w, *_ = orc.equilibrium(0.0, 0.0, T, constraints=13)
+    q = -rho * Cp * nu * dT
+    mom = ((f - rho * w) * v[:, 0]).sum()
+    assert abs(mom - (2.0 - Cp) / (Cp * T) * q) < 1e-15
+    if gamma == 2.0:
+        assert abs(mom) < 1e-16
