@@ -66,13 +66,16 @@ __device__ __forceinline__ double weight13(const double (&l)[kM13]) {
   return exp_cw(-exponent13<cx49(K), cy49(K)>(l));
 }
 
-// Power moments mu[p][q], p + q <= 8, of the weights of l; returns
-// mu[0][0] = sum_i w_i.
+// Power moments mu[p][q], p + q <= 8, of the weights of l (mu[0][0] is
+// sum_i w_i).  Along a row y the exponent splits into a part even in x,
+// A(y) + x^2 B(y) + x^4 l10, and an odd one, x C(y) + x^3 D(y), so that
+// each +-x pair costs two products and a sum and a difference.
 __device__ __forceinline__ void power_moments13(const double (&l)[kM13], double (&mu)[9][9]) {
   static_for<0, 9>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
     static_for<0, 9 - p>([&](auto qc) { mu[p][decltype(qc)::value] = 0.0; });
   });
+  const double l1012 = l[10] + l[12];
   // r[p] = sum_x x^p w(x, y) of row y, for the rows y and -y together
   static_for<0, 4>([&](auto yc) {
     constexpr int y = decltype(yc)::value;
@@ -80,12 +83,23 @@ __device__ __forceinline__ void power_moments13(const double (&l)[kM13], double 
     static_for<0, (y == 0 ? 1 : 2)>([&](auto sc) {
       constexpr int yy = decltype(sc)::value == 0 ? y : -y;
       double r[9];
-      const double w0 = exp_cw(-exponent13<0, yy>(l));
+      // l0 + l2 y + l5 y^2 + l9 y^3 + l12 y^4; l3 + l7 y + (l10 + l12) y^2;
+      // l1 + l4 y + l8 y^2 + l11 y^3; l6 + l11 y
+      const double A = cmad<yy * yy * yy * yy>(
+          cmad<yy * yy * yy>(cmad<yy * yy>(cmad<yy>(l[0], l[2]), l[5]), l[9]), l[12]);
+      const double B = cmad<yy * yy>(cmad<yy>(l[3], l[7]), l1012);
+      const double C = cmad<yy * yy * yy>(cmad<yy * yy>(cmad<yy>(l[1], l[4]), l[8]), l[11]);
+      const double Dd = cmad<yy>(l[6], l[11]);
+      const double w0 = exp_cw(-A);
       double S[4], D[4];
       static_for<1, 4>([&](auto xc) {
         constexpr int x = decltype(xc)::value;
-        const double wp = exp_cw(-exponent13<x, yy>(l));
-        const double wm = exp_cw(-exponent13<-x, yy>(l));
+        const double even = __builtin_fma(static_cast<double>(x * x * x * x), l[10],
+                                          __builtin_fma(static_cast<double>(x * x), B, A));
+        const double odd = __builtin_fma(static_cast<double>(x * x * x), Dd,
+                                         static_cast<double>(x) * C);
+        const double wp = exp_cw(-(even + odd));
+        const double wm = exp_cw(-(even - odd));
         S[x] = wp + wm;
         D[x] = wp - wm;
       });
@@ -230,9 +244,13 @@ __device__ __forceinline__ NewtonOut solve_equilibrium13(double ux, double uy, d
     power_moments13(l, mu);
     const double z = mu[0][0];
     if (!(z > 1e-300) || !(z < 1e300)) return out;
-    l[0] = log(z);  // sum_i w_i = 1
+    l[0] = log(z);  // sum_i w_i = 1: every moment scales by 1 / z
+    const double iz = rcp64(z);
+    static_for<0, 9>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      static_for<0, 9 - p>([&](auto qc) { mu[p][decltype(qc)::value] *= iz; });
+    });
   }
-  power_moments13(l, mu);
   double psi = mu[0][0];
 #pragma unroll
   for (int a = 0; a < kM13; ++a) psi += l[a] * m[a];
