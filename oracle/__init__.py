@@ -28,7 +28,8 @@ class Params(C.Structure):
                 ("nu", C.c_double), ("shift_mode", C.c_int), ("fixed_ux", C.c_int),
                 ("fixed_uy", C.c_int), ("halfwidth", C.c_double),
                 ("newton_tol", C.c_double), ("newton_max_iter", C.c_int),
-                ("max_abs_shift", C.c_int), ("sensor", C.c_int), ("constraints", C.c_int)]
+                ("max_abs_shift", C.c_int), ("sensor", C.c_int), ("constraints", C.c_int),
+                ("prandtl", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -139,9 +140,9 @@ def select(u, Uprev, halfwidth=0.5):
 
 def make_params(nx, ny, gamma=1.4, nu=1e-3, shift_mode=0, fixed_U=(0, 0),
                 halfwidth=0.5, newton_tol=1e-12, newton_max_iter=100,
-                max_abs_shift=6, sensor=0, constraints=8) -> Params:
+                max_abs_shift=6, sensor=0, constraints=8, prandtl=1.0) -> Params:
     return Params(nx, ny, gamma, nu, shift_mode, fixed_U[0], fixed_U[1], halfwidth,
-                  newton_tol, newton_max_iter, max_abs_shift, sensor, constraints)
+                  newton_tol, newton_max_iter, max_abs_shift, sensor, constraints, prandtl)
 
 
 def grad_populations(params: Params, rho, ux, uy, T, du, dT, L, post):

@@ -338,6 +338,71 @@ static int lattice_of(const orc_params* p) { return orc_lattice_of(constraints_o
  * tau = 1/2 + nu / T (App. E). */
 #define ORC_GRAD_G_COEFF 2.0
 
+/* Prandtl number of a simulation: 1 (BGK) unless set. */
+static double prandtl_of(const orc_params* p) { return p->prandtl > 0.0 ? p->prandtl : 1.0; }
+
+/* Heat flux of populations f, g of lattice Q in the frame moving with the
+ * fluid: q_a = (1/2) sum_i cbar_ia (|cbar_i|^2 f_i + g_i), cbar_i = xi_i - u'
+ * (lattice frame, u' the peculiar velocity). */
+static void heat_flux(int Q, const double* f, const double* g, double upx, double upy,
+                      double q[2]) {
+  q[0] = 0.0;
+  q[1] = 0.0;
+  for (int i = 0; i < Q; ++i) {
+    double cx = cx_of(Q, i) - upx, cy = cy_of(Q, i) - upy;
+    double h = (cx * cx + cy * cy) * f[i] + g[i];
+    q[0] += 0.5 * cx * h;
+    q[1] += 0.5 * cy * h;
+  }
+}
+
+/* Flexible-Prandtl collision, eq. (Shakhov) (App. E, Rykov's model with
+ * elastic collisions): BGK plus (1/tau - 1/tau_Pr) h_eq phi_S, with q the
+ * heat flux of the populations being collided.  Reading: the printed term
+ * shapes are the monatomic ones with Cp put in place of the translational
+ * (D + 2)/2 and an extra factor 2 T^2 in the g term; as printed the f term
+ * carries momentum (2 - Cp)/(Cp T) q and the pair carries a fraction of q.
+ * Here
+ *   phi_S,f = q.cbar / (rho Cp T^2) (|cbar|^2 / (2T) - (D + 2)/2),
+ *   phi_S,g = q.cbar / (rho Cp T^2),
+ * which, with the Maxwellian's moments (up to sixth order), carry no mass,
+ * momentum or energy and together the heat flux q (the f term 2/Cp of it,
+ * the g term (Cv - 1)/Cp), so that the heat flux relaxes with tau_Pr; they
+ * equal the printed ones for a monatomic gas (Cp = 2, g_eq = 0).  On a
+ * lattice whose equilibrium moments differ from the Maxwellian's beyond the
+ * enforced ones, f_eq phi_S,f is made free of mass, momentum and energy by
+ * subtracting its projection on 1, cbar_x, cbar_y, |cbar|^2 in the inner
+ * product weighted by f_eq (D2Q21 with 8 constraints fixes moments up to
+ * the third order; D2Q49 with 13 up to the contracted fourth, so there
+ * only the energy part, a fifth-order moment, is left); the g term needs none
+ * (g carries no momentum, and its mass and energy vanish with the first
+ * moment of f_eq).  tau_Pr = 1/2 + (tau - 1/2)/Pr, i.e. 1/2 + nu/(Pr T)
+ * without the sensor. */
+static void shakhov_terms(const orc_params* p, int Q, const double* w, double upx, double upy,
+                          double rho, double T, const double q[2], double* sf, double* sg) {
+  double Cp = p->gamma / (p->gamma - 1.0);
+  double G[ORC_MMAX][ORC_MMAX], r[ORC_MMAX], beta[ORC_MMAX];
+  memset(G, 0, sizeof G);
+  memset(r, 0, sizeof r);
+  for (int i = 0; i < Q; ++i) {
+    double cx = cx_of(Q, i) - upx, cy = cy_of(Q, i) - upy, c2 = cx * cx + cy * cy;
+    double a = (q[0] * cx + q[1] * cy) / (rho * Cp * T * T);
+    double e[4] = {1.0, cx, cy, c2};
+    sf[i] = a * (c2 / (2.0 * T) - 0.5 * (ORC_D + 2));
+    sg[i] = a;
+    double feq = rho * w[i];
+    for (int j = 0; j < 4; ++j) {
+      r[j] += feq * sf[i] * e[j];
+      for (int k = 0; k < 4; ++k) G[j][k] += feq * e[j] * e[k];
+    }
+  }
+  if (solve(4, G, r, beta)) return; /* singular only for a degenerate f_eq */
+  for (int i = 0; i < Q; ++i) {
+    double cx = cx_of(Q, i) - upx, cy = cy_of(Q, i) - upy;
+    sf[i] -= beta[0] + beta[1] * cx + beta[2] * cy + beta[3] * (cx * cx + cy * cy);
+  }
+}
+
 static void grad_phi(const orc_params* p, int i, double rho, double ux, double uy,
                      double T, const double* du, const double* dT, int Lx, int Ly,
                      double* phif, double* phig) {
@@ -350,7 +415,7 @@ static void grad_phi(const orc_params* p, int i, double rho, double ux, double u
   double sxx = -mu * (2.0 * du[0] - (2.0 / ORC_D) * div);
   double syy = -mu * (2.0 * du[3] - (2.0 / ORC_D) * div);
   double sxy = -mu * (du[1] + du[2]);
-  double kappa = rho * Cp * p->nu;
+  double kappa = rho * Cp * p->nu / prandtl_of(p);
   double qx = -kappa * dT[0], qy = -kappa * dT[1];
   double qc = qx * cbx + qy * cby;
   double c2 = cbx * cbx + cby * cby;
@@ -371,6 +436,32 @@ int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
   if (rc) return rc;
   double tau = 0.5 + p->nu / T;
   double k = post ? (1.0 - 1.0 / tau) : 1.0;
+  double Pr = prandtl_of(p);
+  if (post && Pr != 1.0) {
+    /* eq. (Shakhov) applied to the Grad populations (App. E) */
+    double fg[ORC_QMAX] = {0}, gg[ORC_QMAX] = {0}, q[2];
+    double upx = ux - Lx, upy = uy - Ly;
+    for (int i = 0; i < Q; ++i) {
+      double phif, phig;
+      grad_phi(p, i, rho, ux, uy, T, du, dT, Lx, Ly, &phif, &phig);
+      double feq = rho * w[i];
+      double geq = (2.0 * Cv - ORC_D) * T * feq;
+      fg[i] = feq * (1.0 + phif);
+      gg[i] = geq * (1.0 + phig);
+    }
+    heat_flux(Q, fg, gg, upx, upy, q);
+    double tpr = 0.5 + (tau - 0.5) / Pr;
+    double ks = 1.0 / tau - 1.0 / tpr;
+    double sf[ORC_QMAX], sg[ORC_QMAX];
+    shakhov_terms(p, Q, w, upx, upy, rho, T, q, sf, sg);
+    for (int i = 0; i < Q; ++i) {
+      double feq = rho * w[i];
+      double geq = (2.0 * Cv - ORC_D) * T * feq;
+      f[i] = feq + k * (fg[i] - feq) + ks * feq * sf[i];
+      g[i] = geq + k * (gg[i] - geq) + ks * geq * sg[i];
+    }
+    return ORC_OK;
+  }
   for (int i = 0; i < Q; ++i) {
     double phif, phig;
     grad_phi(p, i, rho, ux, uy, T, du, dT, Lx, Ly, &phif, &phig);
@@ -466,7 +557,8 @@ orc_sim* orc_create(const orc_params* p) {
       (p->constraints != 0 && p->constraints != 4 && p->constraints != 8 &&
        p->constraints != 13) ||
       p->shift_mode < 0 || p->shift_mode > 3 ||
-      (p->shift_mode == 3 && !(p->halfwidth < 1.0)))
+      (p->shift_mode == 3 && !(p->halfwidth < 1.0)) || !(p->prandtl >= 0.0) ||
+      !(p->prandtl < 1e3))
     return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   if (!s) return NULL;
@@ -603,11 +695,27 @@ static int collide_all(orc_sim* s) {
     /* BGK collision, eq. (coll), tau = 1/2 + nu / T (App. E) */
     double tau = 0.5 + p->nu / T;
     if (p->sensor) tau *= sensor_alpha(Q, f, rho, w);
-    for (int i = 0; i < Q; ++i) {
-      double feq = rho * w[i];
-      double geq = (2.0 * Cv - ORC_D) * T * feq;
-      s->f[i * N + n] = f[i] - (f[i] - feq) / tau;
-      s->g[i * N + n] = g[i] - (g[i] - geq) / tau;
+    if (prandtl_of(p) != 1.0) {
+      /* flexible Prandtl number, eq. (Shakhov) */
+      double q[2];
+      heat_flux(Q, f, g, upx, upy, q);
+      double tpr = 0.5 + (tau - 0.5) / prandtl_of(p);
+      double ks = 1.0 / tau - 1.0 / tpr;
+      double sf[ORC_QMAX], sg[ORC_QMAX];
+      shakhov_terms(p, Q, w, upx, upy, rho, T, q, sf, sg);
+      for (int i = 0; i < Q; ++i) {
+        double feq = rho * w[i];
+        double geq = (2.0 * Cv - ORC_D) * T * feq;
+        s->f[i * N + n] = f[i] - (f[i] - feq) / tau + ks * feq * sf[i];
+        s->g[i * N + n] = g[i] - (g[i] - geq) / tau + ks * geq * sg[i];
+      }
+    } else {
+      for (int i = 0; i < Q; ++i) {
+        double feq = rho * w[i];
+        double geq = (2.0 * Cv - ORC_D) * T * feq;
+        s->f[i * N + n] = f[i] - (f[i] - feq) / tau;
+        s->g[i * N + n] = g[i] - (g[i] - geq) / tau;
+      }
     }
     s->mac1[4 * n + 0] = rho;
     s->mac1[4 * n + 1] = ux;

@@ -57,6 +57,9 @@ typedef struct {
   int constraints;       /* 8 (or 0): eq. (8moments); 4: mass, momentum and energy
                             only, eq. (feqNum_4Mom); 13: eqs. (G0)-(G4yyaa) on the
                             D2Q49 lattice (the paper's reference model) */
+  double prandtl;        /* 0 or 1: BGK collision, eq. (coll); otherwise the
+                            flexible-Prandtl collision of eq. (Shakhov) with
+                            Pr = nu / (thermal diffusivity) */
 } orc_params;
 
 typedef struct {
