@@ -94,6 +94,17 @@ typedef struct {
                                 fourth-order ones, 13 x 13 solve from the lattice
                                 Maxwellian.  FP64 only, shift modes 0-2, default
                                 schedule, not in lbm_step_batched */
+  double prandtl;            /* Prandtl number nu / (thermal diffusivity): 1 (or 0) =
+                                the BGK collision, eq. (coll); otherwise in [0.01, 1000)
+                                the flexible-Prandtl collision of eq. (Shakhov), App. E:
+                                BGK plus (1/tau - 1/tau_Pr) h_eq phi_S with q the heat
+                                flux of the collided populations, tau_Pr = 1/2 +
+                                (tau - 1/2)/Pr, phi_S the monatomic heat-flux shape
+                                made free of mass, momentum and energy on the lattice
+                                (the printed polyatomic shape carries momentum), and
+                                kappa = rho Cp nu / Pr in the Grad rebuild.  8
+                                constraints, no neighbourhood choice, default schedule,
+                                not in lbm_step_batched */
 } lbm_config;
 
 typedef struct {
@@ -124,7 +135,8 @@ typedef struct {
 
 /* Fills cfg with the defaults used by the paper's tests: gamma 1.4, nu 0,
  * adaptive shifts with half-width 0.5, Newton tolerance 1e-12 and 30
- * iterations, |U| <= 6, FP64, no sensor, no counters, 8 constraints. */
+ * iterations, |U| <= 6, FP64, no sensor, no counters, 8 constraints,
+ * Prandtl number 1. */
 void lbm_default_config(lbm_config* cfg, int32_t nx, int32_t ny);
 
 /* Device bytes the context needs for cfg (two population buffers, lattice

@@ -50,7 +50,8 @@ def velocities(constraints=8):
 
 def make_config(nx: int, ny: int, precision="fp64", gamma=1.4, nu=0.0, shift_mode="adaptive",
                 fixed_U=(0, 0), halfwidth=0.5, newton_tol=1e-12, newton_max_iter=30,
-                max_abs_shift=6, sensor=False, stats=False, constraints=8) -> _lib.Config:
+                max_abs_shift=6, sensor=False, stats=False, constraints=8,
+                prandtl=1.0) -> _lib.Config:
     cfg = _lib.Config()
     lib.lbm_default_config(C.byref(cfg), int(nx), int(ny))
     cfg.precision = PRECISIONS[precision]
@@ -65,6 +66,7 @@ def make_config(nx: int, ny: int, precision="fp64", gamma=1.4, nu=0.0, shift_mod
     cfg.sensor = int(bool(sensor))
     cfg.collect_stats = int(bool(stats))
     cfg.constraints = int(constraints)
+    cfg.prandtl = float(prandtl)
     return cfg
 
 
@@ -80,8 +82,9 @@ class Sim:
         """schedule: None (library default), a dict of lbm_schedule fields,
         or "auto" (the autotuner's cached choice for this size class,
         tuned on a miss; the library default for the four- and
-        13-constraint sets and the neighbourhood shift choice, which are
-        built for that schedule only)."""
+        13-constraint sets, the neighbourhood shift choice and the
+        flexible-Prandtl collision, which are built for that schedule
+        only)."""
         import torch
         self.torch = torch
         self.device = torch.device("cuda" if device is None else device)
@@ -108,6 +111,7 @@ class Sim:
             # the four-constraint and neighbourhood-choice kernels are built
             # for the default schedule only
             if int(kw.get("constraints", 8)) != 8 or \
+                    float(kw.get("prandtl", 1.0)) not in (0.0, 1.0) or \
                     SHIFT_MODES[kw.get("shift_mode", "adaptive")] == SHIFT_NEIGHBOURHOOD:
                 schedule = None
             else:

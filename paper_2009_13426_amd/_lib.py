@@ -19,7 +19,8 @@ class Config(C.Structure):
                 ("fixed_ux", C.c_int32), ("fixed_uy", C.c_int32),
                 ("shift_halfwidth", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("max_abs_shift", C.c_int32),
-                ("sensor", C.c_int32), ("collect_stats", C.c_int32), ("constraints", C.c_int32)]
+                ("sensor", C.c_int32), ("collect_stats", C.c_int32), ("constraints", C.c_int32),
+                ("prandtl", C.c_double)]
 
 
 class Diag(C.Structure):

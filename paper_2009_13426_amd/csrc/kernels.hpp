@@ -49,6 +49,7 @@ enum : unsigned { kCodeNewton = 1, kCodeNonphysical = 2 };
 struct Phys {
   double nu, Cv, Cp, halfwidth, tol;
   int max_iter, shift_mode, fixed_ux, fixed_uy, max_abs_shift, sensor, stats;
+  double inv_pr;  // 1 / Prandtl number (1: BGK)
 };
 
 struct Grid {
@@ -244,7 +245,7 @@ __device__ __forceinline__ GradState grad_state(double rho, double ux, double uy
   s.sxx = -mu * (2.0 * du[0] - div);  // 2/D = 1
   s.syy = -mu * (2.0 * du[3] - div);
   s.sxy = -mu * (du[1] + du[2]);
-  const double kappa = rho * P.Cp * P.nu;  // unit Prandtl number
+  const double kappa = rho * P.Cp * P.nu * P.inv_pr;  // rho Cp nu / Pr
   s.qx = -kappa * dT[0];
   s.qy = -kappa * dT[1];
   s.rho = rho;
@@ -266,6 +267,67 @@ __device__ __forceinline__ void grad_phi(const GradState& s, double cx, double c
   phif = (s.sxx * cbx * cbx + 2.0 * s.sxy * cbx * cby + s.syy * cby * cby) / (2.0 * s.rho * T2) +
          qc / (s.rho * P.Cp * T2) * (c2 / (2.0 * s.T) - P.Cp);
   phig = kGradGCoeff * qc / (s.rho * P.Cp);
+}
+
+// Flexible-Prandtl collision (eq. Shakhov, App. E) on D2Q21 with the
+// 8-moment equilibrium: BGK plus (1/tau - 1/tau_Pr) h_eq phi_S with q the
+// heat flux (1/2) sum_i cbar_i (|cbar_i|^2 f_i + g_i), cbar = xi - u', of the
+// populations being collided, and
+//   phi_S,f = t - (b0 + b1 cbar_x + b2 cbar_y + b3 |cbar|^2),
+//   t = q.cbar / (rho Cp T^2) (|cbar|^2 / (2T) - 2),  phi_S,g = q.cbar / (rho Cp T^2):
+// t is the monatomic heat-flux shape (the printed one carries momentum with
+// the polyatomic Cp), and the b's remove its projection on the collision
+// invariants in the f_eq-weighted inner product, so that the collision
+// conserves mass, momentum and energy on the lattice.  The Gram matrix of
+// (1, cbar_x, cbar_y, |cbar|^2) is rho [[1, 0, 0, 2T], [0, T, 0, 0],
+// [0, 0, T, 0], [2T, 0, 0, S4 / rho]] by the enforced moments up to the
+// third order, S4 = sum_i f_eq |cbar|^4.
+struct ShakhovCoef {
+  double qx, qy, s0, b0, b1, b2, b3;
+};
+
+// Coefficients from the equilibrium weights, the node's (rho, u', T) and
+// its heat flux q.
+template <typename WeightOf>
+__device__ __forceinline__ ShakhovCoef shakhov_coef(WeightOf&& wk, double rho, double upx,
+                                                    double upy, double T, double qx, double qy,
+                                                    const Phys& P) {
+  ShakhovCoef c;
+  c.qx = qx;
+  c.qy = qy;
+  c.s0 = 1.0 / (rho * P.Cp * T * T);
+  const double h = 0.5 / T;
+  double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0, s4 = 0.0;
+  static_for<0, kQ>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const double cx = plane_cx(k) - upx, cy = plane_cy(k) - upy;
+    const double c2 = cx * cx + cy * cy;
+    const double feq = rho * wk(kc);
+    const double ft = feq * (c.s0 * (qx * cx + qy * cy) * __builtin_fma(c2, h, -2.0));
+    r0 += ft;
+    r1 = __builtin_fma(ft, cx, r1);
+    r2 = __builtin_fma(ft, cy, r2);
+    r3 = __builtin_fma(ft, c2, r3);
+    s4 = __builtin_fma(feq * c2, c2, s4);
+  });
+  const double rT = rho * T;
+  c.b1 = r1 / rT;
+  c.b2 = r2 / rT;
+  const double det = rho * s4 - 4.0 * rT * rT;
+  c.b0 = (s4 * r0 - 2.0 * rT * r3) / det;
+  c.b3 = (rho * r3 - 2.0 * rT * r0) / det;
+  return c;
+}
+
+// phi_S,f and phi_S,g of velocity (cx, cy) (lattice frame, cbar = c - u').
+__device__ __forceinline__ void shakhov_phi(const ShakhovCoef& c, double cx, double cy,
+                                            double upx, double upy, double T, double& sf,
+                                            double& sg) {
+  const double bx = cx - upx, by = cy - upy;
+  const double c2 = bx * bx + by * by;
+  const double a = c.s0 * (c.qx * bx + c.qy * by);
+  sf = a * __builtin_fma(c2, 0.5 / T, -2.0) - (c.b0 + c.b1 * bx + c.b2 * by + c.b3 * c2);
+  sg = a;
 }
 
 // Storage type of the carried moments for population storage type S: S
@@ -303,7 +365,7 @@ __device__ __forceinline__ NewtonOut solve_of(const GuessTable& tb, double ux, d
 // (Lx, Ly), rebuilt at source node s by Grad's ansatz from the moments of
 // s's last collision and central differences of its neighbours' (eq.
 // GradGeneral with h* = h_eq + (1 - 1/tau) h_neq, tau = 1/2 + nu / T(s)).
-template <typename S, int M>
+template <typename S, int M, bool PR = false>
 __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long s, int Lx, int Ly,
                                               int k, double& rf, double& rg, int& iters) {
   const CarryT<S>* mac = static_cast<const CarryT<S>*>(a.carry.mac);
@@ -358,6 +420,34 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
   const double geq = (2.0 * P.Cv - 2.0) * T * feq;
   rf = feq * (1.0 + kf * phif);
   rg = geq * (1.0 + kf * phig);
+  if constexpr (PR) {
+    // eq. (Shakhov) applied to the Grad populations h = h_eq (1 + phi) of
+    // the source (App. E): their heat flux in the receiver's frame, then
+    // the link's share of the term
+    const double upx = ux - Lx, upy = uy - Ly;
+    const double gf = (2.0 * P.Cv - 2.0) * T;
+    double qx = 0.0, qy = 0.0;
+    static_for<0, kQ>([&](auto kc) {
+      constexpr int kk = decltype(kc)::value;
+      double pf, pg;
+      grad_phi(gs, static_cast<double>(plane_cx(kk) + Lx), static_cast<double>(plane_cy(kk) + Ly),
+               P, pf, pg);
+      const double fe = rho * weight_of<kk>(w);
+      const double hf = fe * (1.0 + pf), hg = gf * fe * (1.0 + pg);
+      const double cx = plane_cx(kk) - upx, cy = plane_cy(kk) - upy;
+      const double e = (cx * cx + cy * cy) * hf + hg;
+      qx = __builtin_fma(0.5 * cx, e, qx);
+      qy = __builtin_fma(0.5 * cy, e, qy);
+    });
+    const ShakhovCoef sc = shakhov_coef([&](auto kc) { return weight_of<decltype(kc)::value>(w); },
+                                        rho, upx, upy, T, qx, qy, P);
+    const double tpr = 0.5 + (tau - 0.5) * P.inv_pr;
+    const double ks = 1.0 / tau - 1.0 / tpr;
+    double sf, sg;
+    shakhov_phi(sc, cxk, cyk, upx, upy, T, sf, sg);
+    rf += ks * feq * sf;
+    rg += ks * geq * sg;
+  }
   return 0;
 }
 
@@ -394,7 +484,7 @@ struct PullMap {
 // the node's own slot of the output buffer and are read from there.  The
 // tail prepares the next step: moments of this collision, the mask of the
 // next pull's rebuilt links, and the list of nodes that have any.
-template <typename S, bool STREAM, int BLOCK, int M, bool NBH = false>
+template <typename S, bool STREAM, int BLOCK, int M, bool NBH = false, bool PR = false>
 __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   __shared__ S sh_pop[2 * kQ][BLOCK];
   // FP32 storage: the Newton solve keeps its last factors here for the
@@ -565,6 +655,37 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
       }
       const double om = rcp64(tau);
       const double gfac = (2.0 * P.Cv - 2.0) * T;
+      if constexpr (PR) {
+        // flexible Prandtl number, eq. (Shakhov): heat flux of the pulled
+        // populations, then BGK plus the projected term
+        double qx = 0.0, qy = 0.0;
+        static_for<0, kQ>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double cx = plane_cx(k) - upx, cy = plane_cy(k) - upy;
+          const double e = (cx * cx + cy * cy) * static_cast<double>(sh_pop[k][tid]) +
+                           static_cast<double>(sh_pop[kQ + k][tid]);
+          qx = __builtin_fma(0.5 * cx, e, qx);
+          qy = __builtin_fma(0.5 * cy, e, qy);
+        });
+        const ShakhovCoef sc =
+            shakhov_coef([&](auto kc) { return weight_of<decltype(kc)::value>(w); }, rho, upx,
+                         upy, T, qx, qy, P);
+        const double tpr = 0.5 + (tau - 0.5) * P.inv_pr;
+        const double ks = om - rcp64(tpr);
+        static_for<0, kQ>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double feq = rho * weight_of<k>(w);
+          const double geq = gfac * feq;
+          double sf, sg;
+          shakhov_phi(sc, plane_cx(k), plane_cy(k), upx, upy, T, sf, sg);
+          const double fk = static_cast<double>(sh_pop[k][tid]);
+          const double gk = static_cast<double>(sh_pop[kQ + k][tid]);
+          plane_at(fout + k * N, static_cast<unsigned>(n)) =
+              static_cast<S>(__builtin_fma(om, feq - fk, fk) + ks * feq * sf);
+          plane_at(gout + k * N, static_cast<unsigned>(n)) =
+              static_cast<S>(__builtin_fma(om, geq - gk, gk) + ks * geq * sg);
+        });
+      } else
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         const double feq = rho * weight_of<k>(w);
@@ -620,7 +741,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
 // TILED: each workgroup runs a.tiles consecutive tiles in a loop (the loop
 // keeps kernel arguments live across the body, which costs spills); else
 // one tile per workgroup.
-template <typename S, bool STREAM, int BLOCK, bool TILED, int M = kM, bool NBH = false>
+template <typename S, bool STREAM, int BLOCK, bool TILED, int M = kM, bool NBH = false,
+          bool PR = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void step_kernel(StepArgs a) {
   const int g = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
@@ -628,10 +750,10 @@ void step_kernel(StepArgs a) {
     for (int t = 0; t < a.tiles; ++t) {
       const int b = g * a.tiles + t;
       if (b >= a.ntiles) break;
-      step_body<S, STREAM, BLOCK, M, NBH>(a, b);
+      step_body<S, STREAM, BLOCK, M, NBH, PR>(a, b);
     }
   } else {
-    step_body<S, STREAM, BLOCK, M, NBH>(a, g);
+    step_body<S, STREAM, BLOCK, M, NBH, PR>(a, g);
   }
 }
 
@@ -642,7 +764,7 @@ void step_kernel(StepArgs a) {
 // receivers' links into (receiver, link) items and hands them out one per
 // lane.  Grid-stride over the list; clears the other list counter for the
 // coming step's appends.
-template <typename S, int M>
+template <typename S, int M, bool PR = false>
 __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
   __shared__ int sh_node[kWaves][64];
   __shared__ int sh_k[kWaves][64];
@@ -714,7 +836,7 @@ __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
                             wrapc(xx - (cx + Lx), nx, a.grid.fast_x);
         double rf, rg;
         int it;
-        const unsigned code = rebuild_link<S, M>(a, s, Lx, Ly, k, rf, rg, it);
+        const unsigned code = rebuild_link<S, M, PR>(a, s, Lx, Ly, k, rf, rg, it);
         if (code) record_failure(a.diag, a.step, s, code);
         plane_at(fout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rf);
         plane_at(gout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rg);
@@ -732,10 +854,10 @@ __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
   }
 }
 
-template <typename S, int M = kM>
+template <typename S, int M = kM, bool PR = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void rebuild_kernel(RebuildArgs a) {
-  rebuild_body<S, M>(a);
+  rebuild_body<S, M, PR>(a);
 }
 
 // ------------------------------------------------------------ batched

@@ -41,6 +41,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // reference model, D2Q21 otherwise.
 int lattice_q(int constraints) { return constraints == kM13 ? kQ49 : kQ; }
 
+// The flexible-Prandtl collision (eq. Shakhov) is on for Pr other than 1
+// (0 also means BGK).
+bool shakhov_on(const lbm_config* c) { return c->prandtl != 0.0 && c->prandtl != 1.0; }
+
 struct Layout {
   size_t pop_bytes;  // one buffer: f and g, Q planes each
   size_t tag_bytes;
@@ -67,7 +71,10 @@ bool config_ok(const lbm_config* c) {
          std::abs(c->fixed_ux) <= c->max_abs_shift && std::abs(c->fixed_uy) <= c->max_abs_shift &&
          (c->constraints == kM || c->constraints == 4 ||
           (c->constraints == kM13 && c->precision == LBM_FP64 &&
-           c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD));
+           c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD)) &&
+         c->prandtl >= 0.0 && c->prandtl < 1e3 &&
+         (!shakhov_on(c) || (c->prandtl >= 1e-2 && c->constraints == kM &&
+                             c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD));
 }
 
 Layout layout(const lbm_config* c) {
@@ -207,8 +214,18 @@ const void* step_fn_of(bool tiled) {
 // tiling and constraint count; nullptr for a combination that is not built
 // (the four-constraint set is built for 64-lane untiled blocks only).
 const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled, int M,
-                           bool nbh = false) {
+                           bool nbh = false, bool pr = false) {
   const bool f64 = precision == LBM_FP64;
+  if (pr) {  // flexible Prandtl number: default schedule, 8 constraints
+    if (block != 64 || tiled || M != kM || nbh) return nullptr;
+    if (f64)
+      return stream_pass
+                 ? reinterpret_cast<const void*>(&step_kernel<double, true, 64, false, kM, false, true>)
+                 : reinterpret_cast<const void*>(&step_kernel<double, false, 64, false, kM, false, true>);
+    return stream_pass
+               ? reinterpret_cast<const void*>(&step_kernel<float, true, 64, false, kM, false, true>)
+               : reinterpret_cast<const void*>(&step_kernel<float, false, 64, false, kM, false, true>);
+  }
   if (M == kM13) {  // reference model: FP64, 64-lane untiled blocks
     if (!f64 || block != 64 || tiled || nbh) return nullptr;
     return stream_pass ? reinterpret_cast<const void*>(&step49_kernel<true>)
@@ -275,8 +292,12 @@ const void* step_batched_fn(int precision, int block, int M) {
   return nullptr;
 }
 
-const void* rebuild_fn(int precision, int M) {
+const void* rebuild_fn(int precision, int M, bool pr = false) {
   const bool f64 = precision == LBM_FP64;
+  if (pr)
+    return M != kM ? nullptr
+                   : f64 ? reinterpret_cast<const void*>(&rebuild_kernel<double, kM, true>)
+                         : reinterpret_cast<const void*>(&rebuild_kernel<float, kM, true>);
   if (M == kM13) return f64 ? reinterpret_cast<const void*>(&rebuild49_kernel) : nullptr;
   if (M == 4)
     return f64 ? reinterpret_cast<const void*>(&rebuild_kernel<double, 4>)
@@ -324,7 +345,7 @@ Launch<StepArgs> step_launch(const lbm_ctx* c, int src, int dst, bool stream_pas
   a.tiles = stream_pass ? c->sched.tiles_per_block : 1;
   a.remap = stream_pass ? c->sched.xcd_remap : 1;
   L.fn = step_kernel_fn(c->cfg.precision, stream_pass, B, a.tiles > 1, c->cfg.constraints,
-                        c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD);
+                        c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD, shakhov_on(&c->cfg));
   L.grid = dim3(static_cast<unsigned>((a.ntiles + a.tiles - 1) / a.tiles));
   L.block = dim3(B);
   return L;
@@ -345,7 +366,7 @@ Launch<RebuildArgs> rebuild_launch(const lbm_ctx* c, int src, int dst, int step)
   a.table = c->table;
   a.step = step;
   a.diag = c->diag();
-  L.fn = rebuild_fn(c->cfg.precision, c->cfg.constraints);
+  L.fn = rebuild_fn(c->cfg.precision, c->cfg.constraints, shakhov_on(&c->cfg));
   L.grid = dim3(static_cast<unsigned>(c->sched.rebuild_blocks));
   L.block = dim3(kBlock);
   return L;
@@ -454,7 +475,8 @@ bool same_config(const lbm_config& a, const lbm_config& b) {
          a.fixed_uy == b.fixed_uy && a.shift_halfwidth == b.shift_halfwidth &&
          a.newton_tol == b.newton_tol && a.newton_max_iter == b.newton_max_iter &&
          a.max_abs_shift == b.max_abs_shift && a.sensor == b.sensor &&
-         a.collect_stats == b.collect_stats && a.constraints == b.constraints;
+         a.collect_stats == b.collect_stats && a.constraints == b.constraints &&
+         a.prandtl == b.prandtl;
 }
 
 // Default and checked schedules.
@@ -466,9 +488,9 @@ bool schedule_ok(const lbm_ctx* c, const lbm_schedule* s) {
   if (!s) return false;
   const bool tiled = s->tiles_per_block > 1;
   if (!step_kernel_fn(c->cfg.precision, true, s->step_block, tiled, c->cfg.constraints,
-                      c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD))
+                      c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD, shakhov_on(&c->cfg)))
     return false;
-  if (c->cfg.constraints != kM13 &&
+  if (c->cfg.constraints != kM13 && !shakhov_on(&c->cfg) &&
       !step_batched_fn(c->cfg.precision, s->step_block, c->cfg.constraints))
     return false;
   const long long tiles = (c->grid.N + s->step_block - 1) / s->step_block;
@@ -549,6 +571,7 @@ void lbm_default_config(lbm_config* c, int32_t nx, int32_t ny) {
   c->sensor = 0;
   c->collect_stats = 0;
   c->constraints = kM;
+  c->prandtl = 1.0;
 }
 
 size_t lbm_workspace_bytes(const lbm_config* cfg) {
@@ -598,6 +621,7 @@ lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, s
   c->phys.max_abs_shift = cfg->max_abs_shift;
   c->phys.sensor = cfg->sensor;
   c->phys.stats = cfg->collect_stats;
+  c->phys.inv_pr = shakhov_on(cfg) ? 1.0 / cfg->prandtl : 1.0;
   c->nblocks = L.nparts;
   c->sched.step_block = cfg->precision == LBM_FP64 ? step_block<double>() : step_block<float>();
   c->sched.tiles_per_block = 1;
@@ -912,7 +936,8 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
   for (int32_t k = 0; k < n; ++k) {
     lbm_ctx* c = ctxs[k];
     if (!c || nsteps[k] < 0) return LBM_ERR_ARG;
-    if (c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD || c->cfg.constraints == kM13)
+    if (c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD || c->cfg.constraints == kM13 ||
+        shakhov_on(&c->cfg))
       return LBM_ERR_ARG;
     if (c->cfg.precision != ctxs[0]->cfg.precision ||
         c->cfg.constraints != ctxs[0]->cfg.constraints || c->stream != ctxs[0]->stream ||
