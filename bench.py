@@ -192,8 +192,9 @@ def main():
                          "(cached; tuned before the timed region on a miss) or the library "
                          "default")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip timing the four-constraint equilibrium variant (FP32 storage) "
-                         "and the reference model (D2Q49, 13 constraints, FP64)")
+                    help="skip timing the four-constraint equilibrium variant (FP32 storage), "
+                         "the flexible-Prandtl collision (FP32, Pr = 0.71) and the reference "
+                         "model (D2Q49, 13 constraints, FP64)")
     ap.add_argument("--graph-chunk", type=int, default=10,
                     help="steps per HIP graph replayed in the timed region (even)")
     ap.add_argument("--forms", default="fp32,fp64")
@@ -249,6 +250,15 @@ def main():
             equilibrium="mass, momentum and energy constraints only (4 x 4 solve)")
         print(f"[bench] fp32 four constraints: {v['mlups']:.1f} MLUPS", file=sys.stderr,
               flush=True)
+        print("[bench] timing the flexible-Prandtl collision (fp32, Pr = 0.71)",
+              file=sys.stderr, flush=True)
+        v = time_form(lbm, torch, wl, "fp32", args.steps, args.warmup, None, args.graph_chunk,
+                      prandtl=0.71)
+        variants["fp32_prandtl_0.71"] = dict(
+            mlups=round(v["mlups"], 2), kernel_ms=round(v["kernel_ms"], 4),
+            rebuild_ms=round(v["rebuild_ms"], 4), status=v["status"],
+            collision="eq. (Shakhov) at Pr = 0.71, 8 constraints")
+        print(f"[bench] fp32 Pr = 0.71: {v['mlups']:.1f} MLUPS", file=sys.stderr, flush=True)
         # the reference model is about ten times slower per node: fewer steps
         rsteps, rwarm = min(args.steps, 20), min(args.warmup, 4)
         print(f"[bench] timing the reference model (D2Q49, 13 constraints, fp64), "
