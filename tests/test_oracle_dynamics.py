@@ -267,8 +267,8 @@ def test_printed_heat_flux_terms_carry_a_fraction_of_q(orc):
     moment sum xi_x^2 f_eq = rho T), i.e. 0.42 q at T = 0.7 instead of the
     internal-energy share; the f term adds about -0.27 q on this lattice, so
     the state carries ~0.15 q in total.  The same term forms make up the
-    flexible-Prandtl correction of App. (PrandtlExtension), which is why that
-    collision is not built on them."""
+    flexible-Prandtl correction of App. E, which is why that collision is
+    built on corrected shapes instead (test_oracle_prandtl.py)."""
     v = orc.velocities().astype(float)
     nu, rho, T, dT = 0.05, 1.0, 0.7, 0.01
     p = orc.make_params(8, 8, nu=nu)
