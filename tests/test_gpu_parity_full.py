@@ -49,9 +49,9 @@ def sample_centres(wl, count, seed):
     return pts
 
 
-def gpu_values(lbm, wl, steps, precision, pts):
+def gpu_values(lbm, wl, steps, precision, pts, **over):
     import torch
-    sim = lbm.Sim.from_workload(wl, precision=precision)
+    sim = lbm.Sim.from_workload(wl, precision=precision, **over)
     sim.step(steps)
     m = sim.macros()
     ys = torch.tensor([p[1] for p in pts], device=m["rho"].device)
@@ -63,12 +63,12 @@ def gpu_values(lbm, wl, steps, precision, pts):
     return out
 
 
-def oracle_values(orc, wl, steps, pts):
+def oracle_values(orc, wl, steps, pts, **over):
     half = steps * REACH + 8
     out = {k: [] for k in ("rho", "ux", "uy", "T", "Ucx", "Ucy")}
     for (x, y) in pts:
         crop = wl.window(x, y, half)
-        s = orc.Sim.from_workload(crop)
+        s = orc.Sim.from_workload(crop, **over)
         s.step(steps)
         m = s.macros()
         for k in out:
@@ -99,6 +99,28 @@ def test_quadrant_4096_sampled(lbm, orc, precision):
     got = gpu_values(lbm, wl, steps, precision, pts)
     ref = oracle_values(orc, wl, steps, pts)
     compare(got, ref, precision, wl.sensor, f"quadrant_4096/{precision}")
+
+
+# the variants bench.py times on the same draw: (precision, options, steps,
+# sampled nodes); the reference model's crops are few and short (its oracle
+# is about ten times slower per node)
+VARIANTS = {
+    "fp32_constraints4": ("fp32", dict(constraints=4), 6, 16),
+    "fp32_prandtl_0.71": ("fp32", dict(prandtl=0.71), 6, 16),
+    "fp64_prandtl_0.71": ("fp64", dict(prandtl=0.71), 6, 16),
+    "fp64_reference_d2q49_constraints13": ("fp64", dict(constraints=13), 3, 12),
+}
+
+
+@pytest.mark.parametrize("name", list(VARIANTS))
+def test_quadrant_4096_variants_sampled(lbm, orc, name):
+    precision, over, steps, count = VARIANTS[name]
+    wl = W.four_quadrant(4096, steps)
+    pts = sample_centres(wl, count, seed=13)
+    print(f"quadrant 4096^2 {name}, {steps} steps, {len(pts)} sampled nodes", flush=True)
+    got = gpu_values(lbm, wl, steps, precision, pts, **over)
+    ref = oracle_values(orc, wl, steps, pts, **over)
+    compare(got, ref, precision, wl.sensor, f"quadrant_4096/{name}")
 
 
 _VORTEX_REF = {}
