@@ -284,6 +284,7 @@ __device__ __forceinline__ void grad_phi(const GradState& s, double cx, double c
 // third order, S4 = sum_i f_eq |cbar|^4.
 struct ShakhovCoef {
   double qx, qy, s0, b0, b1, b2, b3;
+  double qu, bu, uu, upx, upy, h;  // q.u', b1 u'x + b2 u'y, |u'|^2, u', 1 / (2T)
 };
 
 // Coefficients from the equilibrium weights, the node's (rho, u', T) and
@@ -316,17 +317,26 @@ __device__ __forceinline__ ShakhovCoef shakhov_coef(WeightOf&& wk, double rho, d
   const double det = rho * s4 - 4.0 * rT * rT;
   c.b0 = (s4 * r0 - 2.0 * rT * r3) / det;
   c.b3 = (rho * r3 - 2.0 * rT * r0) / det;
+  c.qu = qx * upx + qy * upy;
+  c.bu = c.b1 * upx + c.b2 * upy;
+  c.uu = upx * upx + upy * upy;
+  c.upx = upx;
+  c.upy = upy;
+  c.h = h;
   return c;
 }
 
-// phi_S,f and phi_S,g of velocity (cx, cy) (lattice frame, cbar = c - u').
-__device__ __forceinline__ void shakhov_phi(const ShakhovCoef& c, double cx, double cy,
-                                            double upx, double upy, double T, double& sf,
-                                            double& sg) {
-  const double bx = cx - upx, by = cy - upy;
-  const double c2 = bx * bx + by * by;
-  const double a = c.s0 * (c.qx * bx + c.qy * by);
-  sf = a * __builtin_fma(c2, 0.5 / T, -2.0) - (c.b0 + c.b1 * bx + c.b2 * by + c.b3 * c2);
+// phi_S,f and phi_S,g of lattice velocity (CX, CY), cbar = c - u'; the
+// products with cbar are expanded in c (integer) so that nothing is shared
+// with the moments pass of shakhov_coef, whose per-velocity values would
+// otherwise stay live into the collision.
+template <int CX, int CY>
+__device__ __forceinline__ void shakhov_phi(const ShakhovCoef& c, double& sf, double& sg) {
+  const double c2 = static_cast<double>(CX * CX + CY * CY) -
+                    2.0 * (CX * c.upx + CY * c.upy) + c.uu;
+  const double a = c.s0 * (c.qx * CX + c.qy * CY - c.qu);
+  sf = a * __builtin_fma(c2, c.h, -2.0) -
+       (c.b0 + (c.b1 * CX + c.b2 * CY - c.bu) + c.b3 * c2);
   sg = a;
 }
 
@@ -443,8 +453,11 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
                                         rho, upx, upy, T, qx, qy, P);
     const double tpr = 0.5 + (tau - 0.5) * P.inv_pr;
     const double ks = 1.0 / tau - 1.0 / tpr;
-    double sf, sg;
-    shakhov_phi(sc, cxk, cyk, upx, upy, T, sf, sg);
+    double sf = 0.0, sg = 0.0;
+    static_for<0, kQ>([&](auto kc) {
+      constexpr int kk = decltype(kc)::value;
+      if (k == kk) shakhov_phi<plane_cx(kk), plane_cy(kk)>(sc, sf, sg);
+    });
     rf += ks * feq * sf;
     rg += ks * geq * sg;
   }
@@ -677,7 +690,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
           const double feq = rho * weight_of<k>(w);
           const double geq = gfac * feq;
           double sf, sg;
-          shakhov_phi(sc, plane_cx(k), plane_cy(k), upx, upy, T, sf, sg);
+          shakhov_phi<plane_cx(k), plane_cy(k)>(sc, sf, sg);
           const double fk = static_cast<double>(sh_pop[k][tid]);
           const double gk = static_cast<double>(sh_pop[kQ + k][tid]);
           plane_at(fout + k * N, static_cast<unsigned>(n)) =
