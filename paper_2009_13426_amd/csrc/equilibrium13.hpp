@@ -223,24 +223,86 @@ __device__ __forceinline__ bool solve13(double (&A)[kTri13], const double (&G)[k
   return true;
 }
 
+// Guess table of the 13-constraint solution over (|u'_x|, |u'_y|, 1/T), the
+// grid of the D2Q21 table, 16 floats per point: l_1 .. l_12 minus the
+// lattice Maxwellian's (l_1 + |u'_x|/T, l_2 + |u'_y|/T, l_3 - 1/(2T), l_4,
+// l_5 - 1/(2T), l_6 .. l_12), 1 (NaN where the solve failed), zeros.
+constexpr int kRec13 = 16;
+
+__global__ __launch_bounds__(256) void table13_kernel(float* out, int nu, int ns, float umax,
+                                                      float smin, float smax, double tol,
+                                                      int max_iter);
+
+// Trilinear guess from the table, multipliers odd in x (odd in y) unfolded
+// by the sign of u'_x (u'_y); the lattice Maxwellian outside the table or
+// next to a corner that did not converge.  l[0] is left for the
+// normalisation.
+__device__ __forceinline__ void table_guess13(const GuessTable& tb, double ux, double uy,
+                                              double iT, double (&l)[kM13]) {
+#pragma unroll
+  for (int a = 0; a < kM13; ++a) l[a] = 0.0;
+  l[1] = -ux * iT;
+  l[2] = -uy * iT;
+  l[3] = 0.5 * iT;
+  l[5] = 0.5 * iT;
+  if (tb.data == nullptr) return;
+  const float a = fabsf(static_cast<float>(ux)), b = fabsf(static_cast<float>(uy));
+  const float s = static_cast<float>(iT);
+  const bool inside = a <= tb.umax && b <= tb.umax && s >= tb.smin && s <= tb.smax;
+  const float fa = fminf(a, tb.umax) * tb.inv_hu, fb = fminf(b, tb.umax) * tb.inv_hu;
+  const float fs = (fminf(fmaxf(s, tb.smin), tb.smax) - tb.smin) * tb.inv_hs;
+  const int ia = min(static_cast<int>(fa), tb.nu - 2);
+  const int ib = min(static_cast<int>(fb), tb.nu - 2);
+  const int is = min(static_cast<int>(fs), tb.ns - 2);
+  const float ta = fa - ia, tb_ = fb - ib, ts = fs - is;
+  float acc[kRec13 - 3];
+#pragma unroll
+  for (int k = 0; k < kRec13 - 3; ++k) acc[k] = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int da = c & 1, db = (c >> 1) & 1, ds = c >> 2;
+    const float4* p = reinterpret_cast<const float4*>(
+        tb.data + (((static_cast<long>(is + ds) * tb.nu + (ib + db)) * tb.nu + (ia + da)) << 4));
+    const float wgt = (da ? ta : 1.0f - ta) * (db ? tb_ : 1.0f - tb_) * (ds ? ts : 1.0f - ts);
+    float v[kRec13 - 3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 r = p[q];
+      if (4 * q + 0 < kRec13 - 3) v[4 * q + 0] = r.x;
+      if (4 * q + 1 < kRec13 - 3) v[4 * q + 1] = r.y;
+      if (4 * q + 2 < kRec13 - 3) v[4 * q + 2] = r.z;
+      if (4 * q + 3 < kRec13 - 3) v[4 * q + 3] = r.w;
+    }
+#pragma unroll
+    for (int k = 0; k < kRec13 - 3; ++k) acc[k] = __builtin_fmaf(wgt, v[k], acc[k]);
+  }
+  if (!inside || !(fabsf(acc[12]) < 1e30f)) return;
+  const double sx = ux < 0.0 ? -1.0 : 1.0, sy = uy < 0.0 ? -1.0 : 1.0;
+  // signs under x -> -x and y -> -y of l_1 .. l_12
+  constexpr int kOddX[kM13] = {0, 1, 0, 0, 1, 0, 1, 0, 1, 0, 0, 1, 0};
+  constexpr int kOddY[kM13] = {0, 0, 1, 0, 1, 0, 0, 1, 0, 1, 0, 1, 0};
+#pragma unroll
+  for (int k = 1; k < kM13; ++k) {
+    double v = acc[k - 1];
+    if (kOddX[k]) v *= sx;
+    if (kOddY[k]) v *= sy;
+    l[k] += v;
+  }
+}
+
 // Multipliers of the equilibrium at (u', T); the weights follow from
-// weight13<k>(l).
-__device__ __forceinline__ NewtonOut solve_equilibrium13(double ux, double uy, double T,
-                                                         double tol, int max_iter,
-                                                         double (&l)[kM13]) {
+// weight13<k>(l).  The start: the table guess (tb.data non-null) or the
+// lattice Maxwellian.
+__device__ __forceinline__ NewtonOut solve_equilibrium13(const GuessTable& tb, double ux,
+                                                         double uy, double T, double tol,
+                                                         int max_iter, double (&l)[kM13]) {
   NewtonOut out{0, false};
   if (!(T > 0.0) || !(T < 1e300) || !(fabs(ux) < 1e300) || !(fabs(uy) < 1e300)) return out;
   double m[kM13];
   targets13(ux, uy, T, m);
   double mu[9][9];
   {
-    const double iT = rcp64(T);
-#pragma unroll
-    for (int a = 0; a < kM13; ++a) l[a] = 0.0;
-    l[1] = -ux * iT;
-    l[2] = -uy * iT;
-    l[3] = 0.5 * iT;
-    l[5] = 0.5 * iT;
+    table_guess13(tb, ux, uy, rcp64(T), l);
     power_moments13(l, mu);
     const double z = mu[0][0];
     if (!(z > 1e-300) || !(z < 1e300)) return out;
@@ -306,6 +368,38 @@ __device__ __forceinline__ NewtonOut solve_equilibrium13(double ux, double uy, d
     // mu now holds the moments of the accepted point
   }
   return out;
+}
+
+}  // namespace lbm
+
+namespace lbm {
+
+// One lane per table point: the solve from the lattice Maxwellian.
+__global__ __launch_bounds__(256) void table13_kernel(float* out, int nu, int ns, float umax,
+                                                      float smin, float smax, double tol,
+                                                      int max_iter) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= nu * nu * ns) return;
+  const int ia = idx % nu, ib = (idx / nu) % nu, is = idx / (nu * nu);
+  const double a = umax * static_cast<double>(ia) / (nu - 1);
+  const double b = umax * static_cast<double>(ib) / (nu - 1);
+  const double s = smin + (smax - smin) * static_cast<double>(is) / (ns - 1);
+  double l[kM13];
+  const GuessTable none{nullptr, 0, 0, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  const NewtonOut no = solve_equilibrium13(none, a, b, 1.0 / s, tol, max_iter, l);
+  float* o = out + static_cast<long>(kRec13) * idx;
+  for (int k = 0; k < kRec13; ++k) o[k] = 0.0f;
+  if (!no.ok) {
+    o[12] = __builtin_nanf("");
+    return;
+  }
+  o[0] = static_cast<float>(l[1] + a * s);
+  o[1] = static_cast<float>(l[2] + b * s);
+  o[2] = static_cast<float>(l[3] - 0.5 * s);
+  o[3] = static_cast<float>(l[4]);
+  o[4] = static_cast<float>(l[5] - 0.5 * s);
+  for (int k = 6; k < kM13; ++k) o[k - 1] = static_cast<float>(l[k]);
+  o[12] = 1.0f;
 }
 
 }  // namespace lbm

@@ -27,8 +27,8 @@ constexpr size_t kAlign = 256;
 constexpr int kMaxBatch = 1024;  // contexts per lbm_step_batched call
 
 // Initial-guess table: |u'_x|, |u'_y| in [0, 2] (step 1/32), 1/T in
-// [0.5, 1/0.3] (35 levels), 8 floats per point (4.7 MB; the states of a flow
-// touch a small part of it).
+// [0.5, 1/0.3] (35 levels), 8 floats per point (4.7 MB; 16 floats, 9.5 MB,
+// for the 13-constraint set; the states of a flow touch a small part of it).
 constexpr int kTabU = 65;
 constexpr int kTabS = 35;
 constexpr float kTabUmax = 2.0f;
@@ -40,6 +40,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Velocities of a constraint set's lattice: D2Q49 for the 13-constraint
 // reference model, D2Q21 otherwise.
 int lattice_q(int constraints) { return constraints == kM13 ? kQ49 : kQ; }
+
+// Bytes of the initial-guess table of a constraint set (8 floats per grid
+// point, 16 for the 13-constraint set).
+size_t table_bytes_of(int constraints) {
+  return static_cast<size_t>(kTabU) * kTabU * kTabS * (constraints == kM13 ? kRec13 : 8) *
+         sizeof(float);
+}
 
 // The flexible-Prandtl collision (eq. Shakhov) is on for Pr other than 1
 // (0 also means BGK).
@@ -113,7 +120,7 @@ Layout layout(const lbm_config* c) {
   L.sums_off = off;
   off += align_up(4 * sizeof(double));
   L.table_off = off;
-  off += align_up(static_cast<size_t>(kTabU) * kTabU * kTabS * 8 * sizeof(float));
+  off += align_up(table_bytes_of(c->constraints));
   L.total = off;
   return L;
 }
@@ -637,10 +644,8 @@ lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, s
   c->table.inv_hs = (kTabS - 1) / (kTabSmax - kTabSmin);
   hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
                      c->carry().counters);
-  const size_t table_bytes = static_cast<size_t>(kTabU) * kTabU * kTabS * 8 * sizeof(float);
-  if (cfg->constraints == kM13) {
-    // the reference model's solve starts from the lattice Maxwellian: no table
-  } else if (like && like->cfg.constraints == cfg->constraints) {
+  const size_t table_bytes = table_bytes_of(cfg->constraints);
+  if (like && like->cfg.constraints == cfg->constraints) {
     if (hipMemcpyAsync(c->ws + L.table_off, like->ws + like->lay.table_off, table_bytes,
                        hipMemcpyDeviceToDevice, c->stream) != hipSuccess) {
       delete c;
@@ -650,7 +655,10 @@ lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, s
     // the table of the context's constraint set, built on the device
     const int pts = kTabU * kTabU * kTabS;
     float* tab = reinterpret_cast<float*>(c->ws + L.table_off);
-    if (cfg->constraints == 4)
+    if (cfg->constraints == kM13)
+      hipLaunchKernelGGL(table13_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream, tab,
+                         kTabU, kTabS, kTabUmax, kTabSmin, kTabSmax, 1e-13, 100);
+    else if (cfg->constraints == 4)
       hipLaunchKernelGGL(table4_kernel, dim3((pts + 255) / 256), dim3(256), 0, c->stream, tab,
                          kTabU, kTabS, kTabUmax, kTabSmin, kTabSmax, 1e-13, 100);
     else

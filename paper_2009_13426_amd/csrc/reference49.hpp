@@ -6,7 +6,8 @@
 //
 //   step49_kernel<STREAM>  one node per lane, 64 lanes per workgroup; the
 //                          98 pulled populations are parked in LDS (50 KB)
-//                          while the 13 x 13 Newton solve holds the
+//                          while the 13 x 13 Newton solve (from the guess
+//                          table of table13_kernel) holds the
 //                          registers; weights are recomputed per plane from
 //                          the multipliers for the collision
 //   rebuild49_kernel       the links of the next pull whose source collided
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kBlock49) void step49_kernel(StepArgs a) {
       });
     }
     if (physical) {
-      const NewtonOut no = solve_equilibrium13(upx, upy, T, P.tol, P.max_iter, l);
+      const NewtonOut no = solve_equilibrium13(a.table, upx, upy, T, P.tol, P.max_iter, l);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -247,7 +248,7 @@ __device__ __forceinline__ unsigned rebuild_link49(const RebuildArgs& a, long lo
     dT[1] = 0.5 * (Sp - Sm);
   }
   double l[kM13];
-  const NewtonOut no = solve_equilibrium13(ux - Lx, uy - Ly, T, P.tol, P.max_iter, l);
+  const NewtonOut no = solve_equilibrium13(a.table, ux - Lx, uy - Ly, T, P.tol, P.max_iter, l);
   iters = no.iters;
   if (!no.ok) return kCodeNewton;
   double wk = 0.0;
@@ -379,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void init49_kernel(InitArgs a) {
   a.tout[n] = tag_pack(Ux, Uy, Ux, Uy);
   double l[kM13];
   if (!code) {
-    const NewtonOut no = solve_equilibrium13(ux - Ux, uy - Uy, T, P.tol, P.max_iter, l);
+    const NewtonOut no = solve_equilibrium13(a.table, ux - Ux, uy - Uy, T, P.tol, P.max_iter, l);
     if (!no.ok) code = kCodeNewton;
   }
   if (code) {
