@@ -102,7 +102,7 @@ typedef struct {
                                 (tau - 1/2)/Pr, phi_S the monatomic heat-flux shape
                                 made free of mass, momentum and energy on the lattice
                                 (the printed polyatomic shape carries momentum), and
-                                kappa = rho Cp nu / Pr in the Grad rebuild.  8
+                                kappa = rho Cp nu / Pr in the Grad rebuild.  8 or 13
                                 constraints, no neighbourhood choice, default schedule,
                                 not in lbm_step_batched */
 } lbm_config;

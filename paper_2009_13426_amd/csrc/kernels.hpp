@@ -287,9 +287,16 @@ struct ShakhovCoef {
   double qu, bu, uu, upx, upy, h;  // q.u', b1 u'x + b2 u'y, |u'|^2, u', 1 / (2T)
 };
 
-// Coefficients from the equilibrium weights, the node's (rho, u', T) and
-// its heat flux q.
-template <typename WeightOf>
+// Velocity set of a lattice for the code shared by D2Q21 and D2Q49.
+struct Lattice21 {
+  static constexpr int Q = kQ;
+  static constexpr int cx(int k) { return plane_cx(k); }
+  static constexpr int cy(int k) { return plane_cy(k); }
+};
+
+// Coefficients from the equilibrium weights (wk(k) for the velocities of
+// lattice L), the node's (rho, u', T) and its heat flux q.
+template <class L = Lattice21, typename WeightOf>
 __device__ __forceinline__ ShakhovCoef shakhov_coef(WeightOf&& wk, double rho, double upx,
                                                     double upy, double T, double qx, double qy,
                                                     const Phys& P) {
@@ -299,9 +306,9 @@ __device__ __forceinline__ ShakhovCoef shakhov_coef(WeightOf&& wk, double rho, d
   c.s0 = 1.0 / (rho * P.Cp * T * T);
   const double h = 0.5 / T;
   double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0, s4 = 0.0;
-  static_for<0, kQ>([&](auto kc) {
+  static_for<0, L::Q>([&](auto kc) {
     constexpr int k = decltype(kc)::value;
-    const double cx = plane_cx(k) - upx, cy = plane_cy(k) - upy;
+    const double cx = L::cx(k) - upx, cy = L::cy(k) - upy;
     const double c2 = cx * cx + cy * cy;
     const double feq = rho * wk(kc);
     const double ft = feq * (c.s0 * (qx * cx + qy * cy) * __builtin_fma(c2, h, -2.0));

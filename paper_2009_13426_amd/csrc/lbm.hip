@@ -80,7 +80,7 @@ bool config_ok(const lbm_config* c) {
           (c->constraints == kM13 && c->precision == LBM_FP64 &&
            c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD)) &&
          c->prandtl >= 0.0 && c->prandtl < 1e3 &&
-         (!shakhov_on(c) || (c->prandtl >= 1e-2 && c->constraints == kM &&
+         (!shakhov_on(c) || (c->prandtl >= 1e-2 && c->constraints != 4 &&
                              c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD));
 }
 
@@ -223,7 +223,7 @@ const void* step_fn_of(bool tiled) {
 const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tiled, int M,
                            bool nbh = false, bool pr = false) {
   const bool f64 = precision == LBM_FP64;
-  if (pr) {  // flexible Prandtl number: default schedule, 8 constraints
+  if (pr && M != kM13) {  // flexible Prandtl number: default schedule, 8 constraints
     if (block != 64 || tiled || M != kM || nbh) return nullptr;
     if (f64)
       return stream_pass
@@ -235,6 +235,9 @@ const void* step_kernel_fn(int precision, bool stream_pass, int block, bool tile
   }
   if (M == kM13) {  // reference model: FP64, 64-lane untiled blocks
     if (!f64 || block != 64 || tiled || nbh) return nullptr;
+    if (pr)
+      return stream_pass ? reinterpret_cast<const void*>(&step49_kernel<true, true>)
+                         : reinterpret_cast<const void*>(&step49_kernel<false, true>);
     return stream_pass ? reinterpret_cast<const void*>(&step49_kernel<true>)
                        : reinterpret_cast<const void*>(&step49_kernel<false>);
   }
@@ -301,11 +304,14 @@ const void* step_batched_fn(int precision, int block, int M) {
 
 const void* rebuild_fn(int precision, int M, bool pr = false) {
   const bool f64 = precision == LBM_FP64;
+  if (M == kM13)
+    return !f64 ? nullptr
+                : pr ? reinterpret_cast<const void*>(&rebuild49_kernel<true>)
+                     : reinterpret_cast<const void*>(&rebuild49_kernel<false>);
   if (pr)
     return M != kM ? nullptr
                    : f64 ? reinterpret_cast<const void*>(&rebuild_kernel<double, kM, true>)
                          : reinterpret_cast<const void*>(&rebuild_kernel<float, kM, true>);
-  if (M == kM13) return f64 ? reinterpret_cast<const void*>(&rebuild49_kernel) : nullptr;
   if (M == 4)
     return f64 ? reinterpret_cast<const void*>(&rebuild_kernel<double, 4>)
                : reinterpret_cast<const void*>(&rebuild_kernel<float, 4>);

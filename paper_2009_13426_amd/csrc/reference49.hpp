@@ -26,6 +26,12 @@ namespace lbm {
 
 constexpr int kBlock49 = 64;
 
+struct Lattice49 {
+  static constexpr int Q = kQ49;
+  static constexpr int cx(int k) { return cx49(k); }
+  static constexpr int cy(int k) { return cy49(k); }
+};
+
 // Wrapped source of plane K for a pull in lattice (ux, uy) at (x, y).
 struct PullMap49 {
   int col[7], row[7];
@@ -46,7 +52,8 @@ __device__ __forceinline__ unsigned long long* mask64(const Carry& c) {
   return reinterpret_cast<unsigned long long*>(c.mask);
 }
 
-template <bool STREAM>
+// PR: the flexible-Prandtl collision (eq. Shakhov) in place of BGK.
+template <bool STREAM, bool PR = false>
 __global__ __launch_bounds__(kBlock49) void step49_kernel(StepArgs a) {
   __shared__ double sh_pop[2 * kQ49][kBlock49];
   __shared__ unsigned long long sh_stat[2 + LBM_HIST_BINS];
@@ -168,14 +175,41 @@ __global__ __launch_bounds__(kBlock49) void step49_kernel(StepArgs a) {
       }
       const double om = rcp64(tau);
       const double gfac = (2.0 * P.Cv - 2.0) * T;
-      static_for<0, kQ49>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        const double feq = rho * weight13<k>(l);
-        const double geq = gfac * feq;
-        const double fk = sh_pop[k][tid], gk = sh_pop[kQ49 + k][tid];
-        plane_at(fout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, feq - fk, fk);
-        plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, geq - gk, gk);
-      });
+      if constexpr (PR) {
+        // heat flux of the pulled populations, then BGK plus the term
+        double qx = 0.0, qy = 0.0;
+        static_for<0, kQ49>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double cx = cx49(k) - upx, cy = cy49(k) - upy;
+          const double e = (cx * cx + cy * cy) * sh_pop[k][tid] + sh_pop[kQ49 + k][tid];
+          qx = __builtin_fma(0.5 * cx, e, qx);
+          qy = __builtin_fma(0.5 * cy, e, qy);
+        });
+        const ShakhovCoef sc = shakhov_coef<Lattice49>(
+            [&](auto kc) { return weight13<decltype(kc)::value>(l); }, rho, upx, upy, T, qx, qy, P);
+        const double ks = om - rcp64(0.5 + (tau - 0.5) * P.inv_pr);
+        static_for<0, kQ49>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double feq = rho * weight13<k>(l);
+          const double geq = gfac * feq;
+          double sf, sg;
+          shakhov_phi<cx49(k), cy49(k)>(sc, sf, sg);
+          const double fk = sh_pop[k][tid], gk = sh_pop[kQ49 + k][tid];
+          plane_at(fout + k * N, static_cast<unsigned>(n)) =
+              __builtin_fma(om, feq - fk, fk) + ks * feq * sf;
+          plane_at(gout + k * N, static_cast<unsigned>(n)) =
+              __builtin_fma(om, geq - gk, gk) + ks * geq * sg;
+        });
+      } else {
+        static_for<0, kQ49>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          const double feq = rho * weight13<k>(l);
+          const double geq = gfac * feq;
+          const double fk = sh_pop[k][tid], gk = sh_pop[kQ49 + k][tid];
+          plane_at(fout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, feq - fk, fk);
+          plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, geq - gk, gk);
+        });
+      }
     }
     a.tout[n] = tag_pack(unx, uny, nux, nuy);
     mask[n] = next_mask;
@@ -214,6 +248,7 @@ __global__ __launch_bounds__(kBlock49) void step49_kernel(StepArgs a) {
 // Post-collision population of plane k in the receiver's lattice (Lx, Ly),
 // rebuilt at source s by Grad's ansatz (eq. GradGeneral) from the moments
 // of s's last collision and central differences of its neighbours'.
+template <bool PR>
 __device__ __forceinline__ unsigned rebuild_link49(const RebuildArgs& a, long long s, int Lx,
                                                    int Ly, int k, double& rf, double& rg,
                                                    int& iters) {
@@ -266,11 +301,39 @@ __device__ __forceinline__ unsigned rebuild_link49(const RebuildArgs& a, long lo
   const double geq = (2.0 * P.Cv - 2.0) * T * feq;
   rf = feq * (1.0 + kf * phif);
   rg = geq * (1.0 + kf * phig);
+  if constexpr (PR) {
+    // eq. (Shakhov) applied to the source's Grad populations (App. E)
+    const double upx = ux - Lx, upy = uy - Ly;
+    const double gf = (2.0 * P.Cv - 2.0) * T;
+    double qx = 0.0, qy = 0.0;
+    static_for<0, kQ49>([&](auto kc) {
+      constexpr int kk = decltype(kc)::value;
+      double pf, pg;
+      grad_phi(gs, static_cast<double>(cx49(kk) + Lx), static_cast<double>(cy49(kk) + Ly), P,
+               pf, pg);
+      const double fe = rho * weight13<kk>(l);
+      const double cx = cx49(kk) - upx, cy = cy49(kk) - upy;
+      const double e = (cx * cx + cy * cy) * fe * (1.0 + pf) + gf * fe * (1.0 + pg);
+      qx = __builtin_fma(0.5 * cx, e, qx);
+      qy = __builtin_fma(0.5 * cy, e, qy);
+    });
+    const ShakhovCoef sc = shakhov_coef<Lattice49>(
+        [&](auto kc) { return weight13<decltype(kc)::value>(l); }, rho, upx, upy, T, qx, qy, P);
+    const double ks = 1.0 / tau - 1.0 / (0.5 + (tau - 0.5) * P.inv_pr);
+    double sf = 0.0, sg = 0.0;
+    static_for<0, kQ49>([&](auto kc) {
+      constexpr int kk = decltype(kc)::value;
+      if (k == kk) shakhov_phi<cx49(kk), cy49(kk)>(sc, sf, sg);
+    });
+    rf += ks * feq * sf;
+    rg += ks * geq * sg;
+  }
   return 0;
 }
 
 // Every (receiver, link) item of the list, one per lane (the receivers'
 // 64-bit masks expanded wave by wave, as in rebuild_kernel).
+template <bool PR = false>
 __global__ __launch_bounds__(kBlock) void rebuild49_kernel(RebuildArgs a) {
   __shared__ int sh_node[kWaves][64];
   __shared__ int sh_k[kWaves][64];
@@ -332,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void rebuild49_kernel(RebuildArgs a) {
             wrapc(xx - (cx49(k) + Lx), nx, a.grid.fast_x);
         double rf, rg;
         int it;
-        const unsigned code = rebuild_link49(a, s, Lx, Ly, k, rf, rg, it);
+        const unsigned code = rebuild_link49<PR>(a, s, Lx, Ly, k, rf, rg, it);
         if (code) record_failure(a.diag, a.step, s, code);
         plane_at(fout + k * N, static_cast<unsigned>(xn)) = rf;
         plane_at(gout + k * N, static_cast<unsigned>(xn)) = rg;

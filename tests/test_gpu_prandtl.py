@@ -76,7 +76,7 @@ def test_graph_replays_and_refusals(lbm):
     with pytest.raises(lbm.LBMError) as e:
         lbm.step_batched([a, b], [2, 2])
     assert e.value.status == lbm.ERR_ARG
-    for bad in (dict(constraints=4), dict(constraints=13, precision="fp64"),
+    for bad in (dict(constraints=4), dict(constraints=13),       # the latter: FP32
                 dict(shift_mode=3, halfwidth=0.75), dict(prandtl=-1.0)):
         kw = dict(precision="fp32", prandtl=0.71)
         kw.update(bad)

@@ -57,6 +57,26 @@ def test_parity_reference_model(lbm, orc, name):
     sim.close()
 
 
+PRANDTL_CASES = {
+    "quadrant_40": (lambda: W.four_quadrant(40, 20), 20),
+    "vortex_40": (lambda: W.isentropic_vortex(40, steps=20), 20),
+    "advected_sod_512x2": (lambda: W.config1(512, 2, 50), 50),
+}
+
+
+@pytest.mark.parametrize("name", list(PRANDTL_CASES))
+def test_parity_reference_model_prandtl(lbm, orc, name):
+    """The flexible-Prandtl collision (App. E) on the reference model."""
+    make, steps = PRANDTL_CASES[name]
+    wl = make()
+    print(f"case {name} D2Q49/M13 Pr=0.71 fp64 {wl.nx}x{wl.ny} steps {steps}", flush=True)
+    _, ref = oracle_run(orc, wl, steps, constraints=13, prandtl=0.71)
+    sim, got = gpu_run(lbm, wl, steps, "fp64", constraints=13, prandtl=0.71)
+    check(orc, got, ref, TOL, f"{name}/M13/Pr0.71")
+    shift_disagreement(got, ref)
+    sim.close()
+
+
 def test_populations_and_conserved_sums(lbm, orc):
     wl = CASES["fixed_U1_24x20"][0]()
     s, _ = oracle_run(orc, wl, 15, constraints=13)
