@@ -270,7 +270,8 @@ __device__ __forceinline__ void grad_phi(const GradState& s, double cx, double c
 }
 
 // Flexible-Prandtl collision (eq. Shakhov, App. E) on D2Q21 with the
-// 8-moment equilibrium: BGK plus (1/tau - 1/tau_Pr) h_eq phi_S with q the
+// 8-moment equilibrium (and on D2Q49 with 13 constraints, which enforce
+// the same low moments): BGK plus (1/tau - 1/tau_Pr) h_eq phi_S with q the
 // heat flux (1/2) sum_i cbar_i (|cbar_i|^2 f_i + g_i), cbar = xi - u', of the
 // populations being collided, and
 //   phi_S,f = t - (b0 + b1 cbar_x + b2 cbar_y + b3 |cbar|^2),

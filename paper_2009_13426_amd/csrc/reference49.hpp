@@ -4,7 +4,8 @@
 // of links whose source collided in another lattice, moments, lattice
 // selection, equilibrium, BGK), over 2 x 49 planes:
 //
-//   step49_kernel<STREAM>  one node per lane, 64 lanes per workgroup; the
+//   step49_kernel<STREAM, PR>  (PR: flexible-Prandtl collision)
+//                          one node per lane, 64 lanes per workgroup; the
 //                          98 pulled populations are parked in LDS (50 KB)
 //                          while the 13 x 13 Newton solve (from the guess
 //                          table of table13_kernel) holds the
