@@ -123,6 +123,24 @@ def test_quadrant_4096_variants_sampled(lbm, orc, name):
     compare(got, ref, precision, wl.sensor, f"quadrant_4096/{name}")
 
 
+def test_quadrant_16384_fp64_planes_above_2gib(lbm, orc):
+    """Large grids: 16384^2 in FP64 puts every population plane at 2 GiB
+    (the kernels address planes by unsigned 32-bit byte offsets, admitted
+    below 4 GiB) and the two buffers at 180 GB of the device's HBM.
+    Sampled nodes, half of them in the last rows (the largest offsets),
+    against the oracle's crops."""
+    steps = 3
+    wl = W.four_quadrant(16384, steps)
+    pts = sample_centres(wl, 6, seed=17)
+    rng = np.random.Generator(np.random.PCG64(19))
+    pts += [(int(x), int(wl.ny - 1 - d)) for x, d in zip(rng.integers(0, wl.nx, 6),
+                                                        rng.integers(0, 4, 6))]
+    print(f"quadrant 16384^2 fp64, {steps} steps, {len(pts)} sampled nodes", flush=True)
+    got = gpu_values(lbm, wl, steps, "fp64", pts)
+    ref = oracle_values(orc, wl, steps, pts)
+    compare(got, ref, "fp64", wl.sensor, "quadrant_16384/fp64")
+
+
 _VORTEX_REF = {}
 
 
