@@ -779,100 +779,109 @@ void step_kernel(StepArgs a) {
 }
 
 // ------------------------------------------------------------ rebuild
-// a2: rebuilds, before a step, every link of that step's pull whose source
-// collided in another lattice, into the receiver's slot of the buffer the
-// step writes.  The list holds the receivers; each wave expands its 64
-// receivers' links into (receiver, link) items and hands them out one per
-// lane.  Grid-stride over the list; clears the other list counter for the
-// coming step's appends.
+// kChunk receivers per wave and pass: a receiver has up to 21 links, so
+// small chunks spread the items over many waves.
+constexpr int kChunk = 16;
+
+// One wave's chunk of a receiver list: receivers [base, base + kChunk) of
+// the count listed, their links expanded into (receiver, link) items with a
+// wave prefix sum and handed out one per lane through the wave's LDS rows
+// (wave-uniform arguments; every lane of the wave takes part).
 template <typename S, int M, bool PR = false>
-__device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
-  __shared__ int sh_node[kWaves][64];
-  __shared__ int sh_k[kWaves][64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const unsigned count = a.carry.counters[(a.step - 1) & 1];
-  if (blockIdx.x == 0 && tid == 0) a.carry.counters[a.step & 1] = 0u;
+__device__ __forceinline__ void rebuild_chunk(const RebuildArgs& a, unsigned count,
+                                              long long base, int* sh_node, int* sh_k) {
+  const int lane = threadIdx.x & 63;
   const Phys& P = a.phys;
   const long long N = a.grid.N;
   const int nx = a.grid.nx;
   S* fout = static_cast<S*>(a.fout);
   S* gout = static_cast<S*>(a.gout);
-  // kChunk receivers per wave and pass: a receiver has up to 21 links, so
-  // small chunks spread the items over many waves
-  constexpr int kChunk = 16;
+  const long long i = base + lane;
+  int node = 0;
+  unsigned msk = 0u;
+  if (lane < kChunk && i < count) {
+    node = a.carry.list[i];
+    msk = a.carry.mask[node];
+  }
+  // exclusive prefix of the link counts over the wave
+  const int cnt = __popc(msk);
+  int v = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  const int total = __shfl(v, 63, 64);
+  const int off = v - cnt;
+  for (int r0 = 0; r0 < total; r0 += 64) {
+    // scatter this round's items to their lanes
+    if (cnt > 0 && off < r0 + 64 && off + cnt > r0) {
+      int j = off;
+      unsigned m = msk;
+      while (m) {
+        const int k = __ffs(m) - 1;
+        m &= m - 1u;
+        if (j >= r0 && j < r0 + 64) {
+          sh_node[j - r0] = node;
+          sh_k[j - r0] = k;
+        }
+        ++j;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (r0 + lane < total) {
+      const int xn = sh_node[lane];
+      const int k = sh_k[lane];
+      const int t = a.tags[xn];
+      const int Lx = min(max(tag_unx(t), -P.max_abs_shift), P.max_abs_shift);
+      const int Ly = min(max(tag_uny(t), -P.max_abs_shift), P.max_abs_shift);
+      const int yx = xn / nx, xx = xn - yx * nx;
+      int cx = 0, cy = 0;
+      static_for<0, kQ>([&](auto kc) {
+        constexpr int kk = decltype(kc)::value;
+        if (k == kk) {
+          cx = plane_cx(kk);
+          cy = plane_cy(kk);
+        }
+      });
+      const long long s = static_cast<long long>(wrapc(yx - (cy + Ly), a.grid.ny, a.grid.fast_y)) * nx +
+                          wrapc(xx - (cx + Lx), nx, a.grid.fast_x);
+      double rf, rg;
+      int it;
+      const unsigned code = rebuild_link<S, M, PR>(a, s, Lx, Ly, k, rf, rg, it);
+      if (code) record_failure(a.diag, a.step, s, code);
+      plane_at(fout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rf);
+      plane_at(gout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rg);
+      if (P.stats) {
+        atomicAdd(&a.diag->mismatched, 1ull);
+        atomicAdd(&a.diag->newton_calls, 1ull);
+        atomicAdd(&a.diag->newton_iters, static_cast<unsigned long long>(it));
+        atomicAdd(&a.diag->hist[it < LBM_HIST_BINS ? it : LBM_HIST_BINS - 1], 1ull);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// a2: rebuilds, before a step, every link of that step's pull whose source
+// collided in another lattice, into the receiver's slot of the buffer the
+// step writes.  The list holds the receivers; grid-stride over its chunks.
+// Clears the other list counter for the coming step's appends.
+template <typename S, int M, bool PR = false>
+__device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
+  __shared__ int sh_node[kWaves][64];
+  __shared__ int sh_k[kWaves][64];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const unsigned count = a.carry.counters[(a.step - 1) & 1];
+  if (blockIdx.x == 0 && tid == 0) a.carry.counters[a.step & 1] = 0u;
   const long long waves = static_cast<long long>(gridDim.x) * kWaves;
   for (long long base = (static_cast<long long>(blockIdx.x) * kWaves + wave) * kChunk; base < count;
-       base += waves * kChunk) {
-    const long long i = base + lane;
-    int node = 0;
-    unsigned msk = 0u;
-    if (lane < kChunk && i < count) {
-      node = a.carry.list[i];
-      msk = a.carry.mask[node];
-    }
-    // exclusive prefix of the link counts over the wave
-    const int cnt = __popc(msk);
-    int v = cnt;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int t = __shfl_up(v, d, 64);
-      if (lane >= d) v += t;
-    }
-    const int total = __shfl(v, 63, 64);
-    const int off = v - cnt;
-    for (int r0 = 0; r0 < total; r0 += 64) {
-      // scatter this round's items to their lanes
-      if (cnt > 0 && off < r0 + 64 && off + cnt > r0) {
-        int j = off;
-        unsigned m = msk;
-        while (m) {
-          const int k = __ffs(m) - 1;
-          m &= m - 1u;
-          if (j >= r0 && j < r0 + 64) {
-            sh_node[wave][j - r0] = node;
-            sh_k[wave][j - r0] = k;
-          }
-          ++j;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (r0 + lane < total) {
-        const int xn = sh_node[wave][lane];
-        const int k = sh_k[wave][lane];
-        const int t = a.tags[xn];
-        const int Lx = min(max(tag_unx(t), -P.max_abs_shift), P.max_abs_shift);
-        const int Ly = min(max(tag_uny(t), -P.max_abs_shift), P.max_abs_shift);
-        const int yx = xn / nx, xx = xn - yx * nx;
-        int cx = 0, cy = 0;
-        static_for<0, kQ>([&](auto kc) {
-          constexpr int kk = decltype(kc)::value;
-          if (k == kk) {
-            cx = plane_cx(kk);
-            cy = plane_cy(kk);
-          }
-        });
-        const long long s = static_cast<long long>(wrapc(yx - (cy + Ly), a.grid.ny, a.grid.fast_y)) * nx +
-                            wrapc(xx - (cx + Lx), nx, a.grid.fast_x);
-        double rf, rg;
-        int it;
-        const unsigned code = rebuild_link<S, M, PR>(a, s, Lx, Ly, k, rf, rg, it);
-        if (code) record_failure(a.diag, a.step, s, code);
-        plane_at(fout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rf);
-        plane_at(gout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rg);
-        if (P.stats) {
-          atomicAdd(&a.diag->mismatched, 1ull);
-          atomicAdd(&a.diag->newton_calls, 1ull);
-          atomicAdd(&a.diag->newton_iters, static_cast<unsigned long long>(it));
-          atomicAdd(&a.diag->hist[it < LBM_HIST_BINS ? it : LBM_HIST_BINS - 1], 1ull);
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-  }
+       base += waves * kChunk)
+    rebuild_chunk<S, M, PR>(a, count, base, sh_node[wave], sh_k[wave]);
 }
 
 template <typename S, int M = kM, bool PR = false>
@@ -947,14 +956,67 @@ __global__ __launch_bounds__(kBlock) void gather_fail_keys_kernel(const JobArgs*
   if (k < njobs) out[k] = jobs[k].diag->fail_key;
 }
 
-// Rebuilds of step s for every job of a batch, each job's list spread over
-// the whole grid in turn.
+// Rebuilds of step s for every job of a batch as one flat index space: the
+// chunks of every job's receiver list, numbered job after job (a block-wide
+// prefix sum over the jobs' chunk counts in LDS), grid-stride over the
+// waves; a wave finds its chunk's job by binary search.  Small jobs no
+// longer leave the grid idle while each job's list is taken in turn.
+constexpr int kMaxJobs = 1024;
+
 template <typename S, int M = kM>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
 void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
-  for (int k = 0; k < njobs; ++k) {
-    const JobArgs& j = jobs[k];
-    if (s >= j.nsteps || j.phys.shift_mode == 1) continue;
+  __shared__ int sh_node[kWaves][64];
+  __shared__ int sh_k[kWaves][64];
+  __shared__ unsigned sh_first[kMaxJobs + 1];  // first global chunk of each job
+  __shared__ unsigned sh_part[kBlock];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  // chunk counts of the (up to four) jobs of this thread, then a block scan
+  constexpr int kPer = kMaxJobs / kBlock;
+  unsigned local[kPer], sum = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int k = tid * kPer + q;
+    unsigned c = 0;
+    if (k < njobs) {
+      const JobArgs& j = jobs[k];
+      if (s < j.nsteps && j.phys.shift_mode != 1) {
+        const int step = j.step0 + s + 1;
+        const unsigned count = j.carry.counters[(step - 1) & 1];
+        c = (count + kChunk - 1) / kChunk;
+        if (blockIdx.x == 0) j.carry.counters[step & 1] = 0u;
+      }
+    }
+    local[q] = c;
+    sum += c;
+  }
+  sh_part[tid] = sum;
+  __syncthreads();
+  for (int d = 1; d < kBlock; d <<= 1) {
+    const unsigned t = tid >= d ? sh_part[tid - d] : 0u;
+    __syncthreads();
+    sh_part[tid] += t;
+    __syncthreads();
+  }
+  unsigned run = sh_part[tid] - sum;  // exclusive prefix of this thread's jobs
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    sh_first[tid * kPer + q] = run;
+    run += local[q];
+  }
+  if (tid == kBlock - 1) sh_first[kMaxJobs] = sh_part[kBlock - 1];
+  __syncthreads();
+  const unsigned total = sh_first[kMaxJobs];
+  const unsigned waves = gridDim.x * kWaves;
+  for (unsigned g = blockIdx.x * kWaves + wave; g < total; g += waves) {
+    // last job whose first chunk is <= g (jobs without chunks are skipped:
+    // their first equals the next job's)
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sh_first[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const JobArgs& j = jobs[lo];
     const int src = (j.cur + s) & 1, dst = src ^ 1;
     RebuildArgs a;
     a.fout = j.pop[dst];
@@ -966,7 +1028,9 @@ void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
     a.table = j.table;
     a.step = j.step0 + s + 1;
     a.diag = j.diag;
-    rebuild_body<S, M>(a);
+    const unsigned count = j.carry.counters[(a.step - 1) & 1];
+    const long long base = static_cast<long long>(g - sh_first[lo]) * kChunk;
+    rebuild_chunk<S, M>(a, count, base, sh_node[wave], sh_k[wave]);
   }
 }
 

@@ -25,6 +25,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxBatch = 1024;  // contexts per lbm_step_batched call
+static_assert(kMaxBatch <= kMaxJobs, "the batched rebuild's job table holds kMaxJobs");
 
 // Initial-guess table: |u'_x|, |u'_y| in [0, 2] (step 1/32), 1/T in
 // [0.5, 1/0.3] (35 levels), 8 floats per point (4.7 MB; 16 floats, 9.5 MB,
