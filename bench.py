@@ -127,6 +127,27 @@ def stats_pass(lbm, wl, precision, steps):
                 rebuilt_links_per_node=d["mismatched_links"] / nodes)
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Measured device-copy bandwidth (bytes read + written per second) of a
+    plain 1 GiB copy, the best of a few: the practical HBM ceiling beside
+    the vendor's 8 TB/s."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * (mib << 20) / best / 1e9
+
+
 def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
     """The FP64 oracle, as it is, on a bounded sample of the same workload:
     a 641 x 641 periodic crop around the quadrant corner, stepped until about
@@ -278,6 +299,7 @@ def main():
         counters = {f: stats_pass(lbm, wl, f, 5) for f in res}
 
     nodes = wl.nx * wl.ny
+    copy_gbs = copy_bandwidth(torch)
     prof = profile_figures()
     fresh = prof.get("source_sha256") == kernel_sources_digest() and \
         prof.get("size") == str(args.size)
@@ -297,6 +319,8 @@ def main():
                     valu_issue_frac=round(valu * nodes / t_step / VALU_ISSUE_PEAK, 4),
                     hbm=dict(achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                              frac=round(hbm / HBM_PEAK_GBS, 4),
+                             copy_gbs=round(copy_gbs, 1),
+                             frac_of_copy=round(hbm / copy_gbs, 4),
                              bytes_per_node=bytes_per_node(head)))
     serving = None
     if not args.no_serve:
