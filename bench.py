@@ -165,8 +165,14 @@ def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
         n += 2
     dt = time.perf_counter() - t0
     nodes = sample.nx * sample.ny
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=round(nodes * n / dt / 1e6, 4), unit="MLUPS", cores=threads,
-                kind="oracle",
+                kind="oracle", cpu=model, host_cpus=os.cpu_count(),
                 sample=f"{sample.nx}x{sample.ny} periodic crop of the same initial field, "
                        f"{n} steps, FP64, {dt:.1f} s")
 
