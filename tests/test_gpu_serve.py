@@ -77,3 +77,42 @@ def test_late_arrivals_join_the_running_batch(serve):
           f"job1 admitted {r1.admitted * 1e3:.1f} ms finished {r1.finished * 1e3:.1f} ms", flush=True)
     assert r0.status == 0 and r1.status == 0
     assert r1.admitted < r0.finished and r1.finished < r0.finished
+
+
+def test_many_jobs_in_one_batch_equal_alone(serve):
+    """A batch of up to 300 small jobs (more than one job per thread in the
+    batched rebuild's block-wide scan of the jobs' receiver chunks), of
+    uneven sides and step counts, some on one fixed lattice (no rebuilt
+    links) and some finishing before others: every job's fields after the
+    batch equal the job run alone, bit for bit.  Draws whose flow leaves the
+    equilibrium's envelope when run alone (a few small quadrant grids) are
+    left out of the batch."""
+    import paper_2009_13426_amd as lbm
+    rng = np.random.Generator(np.random.PCG64(23))
+    jobs, alone = [], []
+    for j in range(300):
+        n = int(rng.integers(8, 40))
+        if j % 7 == 3:
+            wl = W.uniform(n, n, 1.0, 0.4, -0.2, 0.8, shift_mode=1, fixed_U=(0, 0))
+        elif j % 2 == 0:
+            wl = W.four_quadrant(n, 20, sub=j + 1, mach=0.5 + (j % 5) * 0.2)
+        else:
+            wl = W.isentropic_vortex(n, steps=20, mach=0.5 + (j % 4) * 0.5)
+        k = int(rng.integers(1, 13))
+        a = lbm.Sim.from_workload(wl, precision="fp32")
+        try:
+            a.step(k)
+        except lbm.LBMError:
+            a.close()
+            continue
+        jobs.append((wl, k))
+        alone.append(macros_of(a))
+        a.close()
+    assert len(jobs) > 256
+    sims = [lbm.Sim.from_workload(wl, precision="fp32") for wl, _ in jobs]
+    lbm.step_batched(sims, [k for _, k in jobs])
+    for (wl, k), s, want in zip(jobs, sims, alone):
+        got = macros_of(s)
+        for key in ("rho", "ux", "uy", "T", "Ux", "Uy"):
+            assert np.array_equal(got[key], want[key]), (wl.name, k, key)
+        s.close()
