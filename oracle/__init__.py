@@ -68,6 +68,8 @@ def lib():
         L.orc_grad_populations.restype = C.c_int
         L.orc_select.argtypes = [C.c_double, C.c_int, C.c_double]
         L.orc_select.restype = C.c_int
+        L.orc_sensor_alpha.argtypes = [C.c_double]
+        L.orc_sensor_alpha.restype = C.c_double
         L.orc_create.argtypes = [C.POINTER(Params)]
         L.orc_create.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
@@ -136,6 +138,11 @@ def targets_m(constraints, ux, uy, T):
 
 def select(u, Uprev, halfwidth=0.5):
     return lib().orc_select(float(u), int(Uprev), float(halfwidth))
+
+
+def sensor_alpha(eps):
+    """Relaxation-time factor alpha(eps) of the kinetic sensor (eq. DeltaAvg)."""
+    return lib().orc_sensor_alpha(float(eps))
 
 
 def make_params(nx, ny, gamma=1.4, nu=1e-3, shift_mode=0, fixed_U=(0, 0),

@@ -15,11 +15,12 @@ FLAGS = ["-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
 
 
 def build(verbose: bool = False) -> str:
-    cmd = [os.environ.get("CC", "gcc"), *FLAGS, SRC, "-o", LIB + ".tmp", "-lm"]
+    tmp = f"{LIB}.tmp{os.getpid()}"  # unique: parallel test workers build too
+    cmd = [os.environ.get("CC", "gcc"), *FLAGS, SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(tmp, LIB)
     return LIB
 
 

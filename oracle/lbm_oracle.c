@@ -606,11 +606,26 @@ static void record_failure(orc_sim* s, long n, int rc, int* err) {
   }
 }
 
+/* Relaxation-time factor alpha(eps) of the kinetic sensor (Sec. IV.A.2).
+ * The paper states that dissipation is added above eps = 0.01 but does not
+ * print alpha.  Reading: three levels of added dissipation, alpha = 1.05,
+ * 1.35 and 2 from eps = 0.01, 0.1 and 1 on, each reached by a linear ramp
+ * over the first tenth of its decade (from 1 at eps = 0.01 to 1.05 at
+ * 0.011, from 1.05 at 0.1 to 1.35 at 0.11, from 1.35 at 1 to 2 at 1.1), and
+ * 1 up to 0.01.  alpha is continuous and non-decreasing, so a rounding-level
+ * change of eps changes tau by a rounding-level amount. */
+double orc_sensor_alpha(double eps) {
+  static const double ke[6] = {0.01, 0.011, 0.1, 0.11, 1.0, 1.1};
+  static const double ka[6] = {1.0, 1.05, 1.05, 1.35, 1.35, 2.0};
+  if (!(eps > ke[0])) return 1.0;
+  for (int j = 1; j < 6; ++j)
+    if (eps <= ke[j])
+      return ka[j - 1] + (ka[j] - ka[j - 1]) * (eps - ke[j - 1]) / (ke[j] - ke[j - 1]);
+  return ka[5];
+}
+
 /* Kinetic sensor, eq. (DeltaAvg): eps = (1/V) sum_i |f_i - f_i^eq| / f_i^eq,
- * with tau_f -> tau_f alpha(eps) (Sec. IV.A.2).  The paper gives the
- * threshold 0.01 above which dissipation is added but not alpha itself.
- * Reading: alpha is piecewise constant, 1 below 1e-2, then 1.05, 1.35 and
- * 2 from 1e-1 and 1 upwards. */
+ * with tau_f -> tau_f alpha(eps) (Sec. IV.A.2). */
 static double sensor_alpha(int Q, const double* f, double rho, const double* w) {
   double eps = 0.0;
   for (int i = 0; i < Q; ++i) {
@@ -618,10 +633,7 @@ static double sensor_alpha(int Q, const double* f, double rho, const double* w) 
     eps += fabs(f[i] - feq) / feq;
   }
   eps /= Q;
-  if (eps < 1e-2) return 1.0;
-  if (eps < 1e-1) return 1.05;
-  if (eps < 1.0) return 1.35;
-  return 2.0;
+  return orc_sensor_alpha(eps);
 }
 
 /* Moments, lattice selection, equilibrium and collision for every node.

@@ -11,6 +11,11 @@
  * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
  * shares no code with the GPU path and must never be used as a fallback for it.
  *
+ * Parity unpinned (the paper does not fix them, so the tests pin only their
+ * stated properties): the D2Q21 velocity table (orc_velocities), the printed
+ * coefficient of the Grad g-deviation, and the values of the sensor's
+ * relaxation-time factor (orc_sensor_alpha).
+ *
  * Conventions
  *  - Grid nx * ny, periodic in x and y; node n = y * nx + x.
  *  - Populations are stored SoA: h[i * N + n], i in [0, Q), Q = 21 (or 49
@@ -111,6 +116,10 @@ int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
 /* Lattice shift along one axis for velocity u, previous shift Uprev and
  * selection half-width (0.5 = eq. criterion without history). */
 int orc_select(double u, int Uprev, double halfwidth);
+
+/* Relaxation-time factor alpha(eps) of the kinetic sensor, eq. (DeltaAvg)
+ * (a reading: the paper does not print alpha; see lbm_oracle.c). */
+double orc_sensor_alpha(double eps);
 
 orc_sim* orc_create(const orc_params* p);
 void orc_destroy(orc_sim* s);

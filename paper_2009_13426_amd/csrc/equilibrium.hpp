@@ -23,10 +23,10 @@
 //   solve_fast    start from an interpolated table of lambda - lambda_Maxwell,
 //                 weights carried (not multipliers): later updates
 //                 w *= exp(-delta . phi) by Taylor polynomials of degree 3
-//                 (|delta . phi| < 1e-5) or 7 (< 0.03) and by exp_cw
-//                 otherwise; H is accumulated straight from the weights, one
-//                 +- pair at a time, and its factors are reused for the final
-//                 correction.
+//                 (every |delta . phi| of the wave < 1e-5) or 7 (< 0.03) and
+//                 by exp_cw otherwise; H is accumulated straight from the
+//                 weights, one +- pair at a time, and the factors of the last
+//                 step stay in registers for the final correction.
 // Both stop on the same criterion, so both reach the unique root to rounding.
 #pragma once
 
@@ -69,18 +69,6 @@ __device__ __forceinline__ double exp_cw(double x) {
 #ifndef LBM_EXP_CW
 #define LBM_EXP_CW 1
 #endif
-// Where a Newton solve may keep the LDL^T factors of its last step for the
-// final correction: 36 values per lane, element i at p[i * stride] (LDS),
-// rounded to FP32.  p == nullptr: no stash, the correction refactorises.
-struct FactorStash {
-  float* p;
-  int stride;
-};
-
-// A step whose largest exponent change is below this leaves the Hessian
-// close enough (relative change ~1e-6) for its factors to serve the next
-// iteration's correction.
-constexpr double kStashStep = 1e-5;
 __device__ __forceinline__ double exp_neg(double z) {
 #if LBM_EXP_CW
   return exp_cw(-z);
@@ -151,31 +139,6 @@ __device__ __forceinline__ double expm_tiny(double z) {
   p = __builtin_fma(p, t, 0.5);
   p = __builtin_fma(p, t, 1.0);
   return __builtin_fma(p, t, 1.0);
-}
-
-// largest |d . phi_i| over the velocities
-template <int p = 0>
-__device__ __forceinline__ double max_step_exponent(const double (&d)[kM], double acc) {
-  if constexpr (p == kPairs) {
-    return fmax(acc, fabs(d[0]));
-  } else {
-    double e, o;
-    pair_exponent<p>(d, 0.0, e, o);
-    return max_step_exponent<p + 1>(d, fmax(acc, fabs(e) + fabs(o)));
-  }
-}
-
-// w_i *= exp(-d . phi_i) with the small-argument polynomial
-template <int p = 0>
-__device__ __forceinline__ void poly_update(const double (&d)[kM], Weights& w) {
-  if constexpr (p == 0) w.w0 *= expm_small(d[0]);
-  if constexpr (p < kPairs) {
-    double e, o;
-    pair_exponent<p>(d, 0.0, e, o);
-    w.wp[p] *= expm_small(e + o);
-    w.wm[p] *= expm_small(e - o);
-    poly_update<p + 1>(d, w);
-  }
 }
 
 template <int P, int Qy, int p = 0>
@@ -550,18 +513,21 @@ __device__ __forceinline__ void hessian_direct(const Weights& w, const double (&
   }
 }
 
-// In-place LDL^T; on return the diagonal holds 1/D.
+// In-place LDL^T; on return the diagonal holds 1/D (one reciprocal per
+// pivot: the pivots themselves are kept aside while later columns need them).
 __device__ __forceinline__ bool ldl_factor_inplace(double (&A)[kTri]) {
   bool spd = true;
+  double dg[kM];
 #pragma unroll
   for (int j = 0; j < kM; ++j) {
     double t[kM];
 #pragma unroll
-    for (int k = 0; k < j; ++k) t[k] = A[tri(j, k)] * A[tri(k, k)];  // L_jk d_k
+    for (int k = 0; k < j; ++k) t[k] = A[tri(j, k)] * dg[k];  // L_jk d_k
     double dj = A[tri(j, j)];
 #pragma unroll
     for (int k = 0; k < j; ++k) dj = __builtin_fma(-A[tri(j, k)], t[k], dj);
     spd = spd && (dj > 0.0);
+    dg[j] = dj;
     const double idj = rcp64(dj);
 #pragma unroll
     for (int i = j + 1; i < kM; ++i) {
@@ -570,10 +536,8 @@ __device__ __forceinline__ bool ldl_factor_inplace(double (&A)[kTri]) {
       for (int k = 0; k < j; ++k) v = __builtin_fma(-A[tri(i, k)], t[k], v);
       A[tri(i, j)] = v * idj;
     }
-    A[tri(j, j)] = dj;
+    A[tri(j, j)] = idj;
   }
-#pragma unroll
-  for (int j = 0; j < kM; ++j) A[tri(j, j)] = rcp64(A[tri(j, j)]);
   return spd;
 }
 
@@ -593,29 +557,46 @@ __device__ __forceinline__ void ldl_solve_inplace(const double (&A)[kTri], doubl
   }
 }
 
-// w_i *= F(d . phi_i) for one of the exp(-z) evaluators below.
-template <typename F, int p = 0>
-__device__ __forceinline__ void scale_weights(const double (&d)[kM], Weights& w, F f) {
-  if constexpr (p == 0) w.w0 *= f(d[0]);
+// Even and odd parts of d . phi over the +- pairs (z = e +- o), computed
+// once per step for the update and for its largest magnitude.
+template <int p = 0>
+__device__ __forceinline__ void step_exponents(const double (&d)[kM], double (&e)[kPairs],
+                                               double (&o)[kPairs]) {
   if constexpr (p < kPairs) {
-    double e, o;
-    pair_exponent<p>(d, 0.0, e, o);
-    w.wp[p] *= f(e + o);
-    w.wm[p] *= f(e - o);
-    scale_weights<F, p + 1>(d, w, f);
+    pair_exponent<p>(d, 0.0, e[p], o[p]);
+    step_exponents<p + 1>(d, e, o);
   }
 }
 
-// w_i *= exp(-d . phi_i): the degree-3 polynomial when every |d . phi_i| <
-// 1e-5, the degree-7 one below 0.03, exp otherwise.  One branch per update
-// (lanes of a wave normally agree), not one per weight.
-__device__ __forceinline__ void exp_update(const double (&d)[kM], Weights& w, double big) {
-  if (big < 1e-5) {
-    scale_weights(d, w, [](double z) { return expm_tiny(z); });
-  } else if (big < 0.03) {
-    scale_weights(d, w, [](double z) { return expm_small(z); });
+// w_i *= F(z_i) for one of the exp(-z) evaluators below.
+template <typename F>
+__device__ __forceinline__ void scale_weights(double d0, const double (&e)[kPairs],
+                                              const double (&o)[kPairs], Weights& w, F f) {
+  w.w0 *= f(d0);
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) {
+    w.wp[p] *= f(e[p] + o[p]);
+    w.wm[p] *= f(e[p] - o[p]);
+  }
+}
+
+// w_i *= exp(-d . phi_i): the degree-3 polynomial when every |d . phi_i| of
+// every lane of the wave is below 1e-5, the degree-7 one below 0.03, exp
+// otherwise.  The choice is made for the whole wave (a ballot), so that
+// lanes never split over two evaluators: each one is exact over its range,
+// and a wave runs one of them.
+__device__ __forceinline__ void exp_update(const double (&d)[kM], Weights& w) {
+  double e[kPairs], o[kPairs];
+  step_exponents(d, e, o);
+  double big = fabs(d[0]);
+#pragma unroll
+  for (int p = 0; p < kPairs; ++p) big = fmax(big, fabs(e[p]) + fabs(o[p]));
+  if (__ballot(!(big < 0.03))) {
+    scale_weights(d[0], e, o, w, [](double z) { return exp_neg(z); });
+  } else if (__ballot(!(big < 1e-5))) {
+    scale_weights(d[0], e, o, w, [](double z) { return expm_small(z); });
   } else {
-    scale_weights(d, w, [](double z) { return exp_neg(z); });
+    scale_weights(d[0], e, o, w, [](double z) { return expm_tiny(z); });
   }
 }
 
@@ -644,13 +625,11 @@ __device__ __forceinline__ void constraint_moments(const Weights& w, double (&c)
 
 // Table start, then Newton steps applied to the weights multiplicatively (no
 // multipliers are carried).  Stops on max |G| <= tol with a first-order
-// final correction; when the previous step was small (every |d . phi_i| <
-// 1e-3) that correction reuses the previous factorisation of H, whose
-// relative change is of the size of that step, so the correction is exact
-// to far below the tolerance.
+// final correction, solved with the factors of the last step, which are
+// kept in registers: the residual is at the tolerance, so factors of a
+// Hessian that moved by the size of that step take it to round-off.
 __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux, double uy,
-                                                double T, double tol, int max_iter, Weights& w,
-                                                FactorStash stash = {nullptr, 0}) {
+                                                double T, double tol, int max_iter, Weights& w) {
   NewtonOut out{0, false};
   {
     // The first weights must be of exponential form to full FP64 accuracy:
@@ -686,8 +665,7 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
          : a == 6 ? 2.0 * ux * ET
                   : 2.0 * uy * ET;
   };
-  double A[kTri];
-  bool stashed = false;  // the stash holds the factors of a Hessian close to the current one
+  double A[kTri];  // factors of the last step's Hessian
   for (int it = 0; it < max_iter; ++it) {
     double G[kM];
     constraint_moments(w, G);
@@ -698,12 +676,8 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
     for (int a = 0; a < kM; ++a) r = fmax(r, fabs(G[a]));
     out.iters = it + 1;
     if (!(r < 1e300)) return out;
-    if (r <= tol && stashed) {
-      // final correction with the last step's factors: the residual is at
-      // the tolerance already, so FP32 factors of a Hessian that moved by
-      // ~1e-6 take it to round-off
-#pragma unroll
-      for (int i = 0; i < kTri; ++i) A[i] = static_cast<double>(stash.p[i * stash.stride]);
+    if (r <= tol && it > 0) {
+      // final correction with the last step's factors
       ldl_solve_inplace(A, G);
       linear_update(G, w);
       out.ok = true;
@@ -731,13 +705,7 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
 #pragma unroll
       for (int a = 0; a < kM; ++a) G[a] *= sc;
     }
-    const double big = max_step_exponent(G, 0.0);
-    stashed = stash.p != nullptr && big < kStashStep;
-    if (stashed) {
-#pragma unroll
-      for (int i = 0; i < kTri; ++i) stash.p[i * stash.stride] = static_cast<float>(A[i]);
-    }
-    exp_update(G, w, big);
+    exp_update(G, w);
   }
   return out;
 }
@@ -746,9 +714,8 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
 // from which plain Newton steps do not converge) the globalised solve_robust.
 __device__ __forceinline__ NewtonOut solve_equilibrium(const GuessTable& tb, double ux, double uy,
                                                        double T, double tol, int max_iter,
-                                                       Weights& w,
-                                                       FactorStash stash = {nullptr, 0}) {
-  NewtonOut out = solve_fast(tb, ux, uy, T, tol, max_iter, w, stash);
+                                                       Weights& w) {
+  NewtonOut out = solve_fast(tb, ux, uy, T, tol, max_iter, w);
   if (!out.ok) {
     double l[kM];
     const NewtonOut r = solve_robust(ux, uy, T, tol, max_iter, w, l);

@@ -281,7 +281,7 @@ __device__ __forceinline__ NewtonOut solve_equilibrium4(const GuessTable& tb, do
 #pragma unroll
       for (int a = 0; a < kM; ++a) d[a] *= sc;
     }
-    exp_update(d, w, max_step_exponent(d, 0.0));
+    exp_update(d, w);
   }
   if (ok) {
     out.ok = true;

@@ -371,12 +371,11 @@ __device__ __forceinline__ void carried_uT(const S* mac, const int* tags, long l
 // eq. feqNum_4Mom).
 template <int M>
 __device__ __forceinline__ NewtonOut solve_of(const GuessTable& tb, double ux, double uy,
-                                              double T, const Phys& P, Weights& w,
-                                              FactorStash stash = {nullptr, 0}) {
+                                              double T, const Phys& P, Weights& w) {
   if constexpr (M == 4)
     return solve_equilibrium4(tb, ux, uy, T, P.tol, P.max_iter, w);
   else
-    return solve_equilibrium(tb, ux, uy, T, P.tol, P.max_iter, w, stash);
+    return solve_equilibrium(tb, ux, uy, T, P.tol, P.max_iter, w);
 }
 
 // Post-collision population of velocity plane k in the receiver's lattice
@@ -472,11 +471,20 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
   return 0;
 }
 
-// Kinetic sensor eps = (1/V) sum_i |f_i - f_i^eq| / f_i^eq and the relaxation
-// time factor alpha(eps) (eq. DeltaAvg; alpha is not printed in the paper:
-// piecewise constant 1 / 1.05 / 1.35 / 2 with breaks at 1e-2, 1e-1, 1).
+// Relaxation-time factor alpha of the kinetic sensor eps = (1/V) sum_i
+// |f_i - f_i^eq| / f_i^eq (eq. DeltaAvg).  The paper adds dissipation above
+// eps = 0.01 without printing alpha; here alpha is 1 up to 0.01 and takes the
+// levels 1.05, 1.35 and 2 from 0.01, 0.1 and 1 on, each reached by a linear
+// ramp over the first tenth of its decade.  alpha is continuous, so a
+// rounding-level change of eps changes tau by a rounding-level amount.
 __device__ __forceinline__ double sensor_alpha(double eps) {
-  return eps < 1e-2 ? 1.0 : (eps < 1e-1 ? 1.05 : (eps < 1.0 ? 1.35 : 2.0));
+  if (!(eps > 1e-2)) return 1.0;
+  if (eps <= 1.1e-2) return __builtin_fma(eps - 1e-2, 0.05 / 1e-3, 1.0);
+  if (eps <= 1e-1) return 1.05;
+  if (eps <= 1.1e-1) return __builtin_fma(eps - 1e-1, 0.30 / 1e-2, 1.05);
+  if (eps <= 1.0) return 1.35;
+  if (eps <= 1.1) return __builtin_fma(eps - 1.0, 0.65 / 0.1, 1.35);
+  return 2.0;
 }
 
 // Wrapped source columns and row offsets of node (x, y) for a pull in
@@ -508,10 +516,6 @@ struct PullMap {
 template <typename S, bool STREAM, int BLOCK, int M, bool NBH = false, bool PR = false>
 __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   __shared__ S sh_pop[2 * kQ][BLOCK];
-  // FP32 storage: the Newton solve keeps its last factors here for the
-  // final correction (9 KB per wave; FP64's parking area leaves no room)
-  constexpr bool kStash = std::is_same<S, float>::value && M == 8;
-  __shared__ float sh_fac[kStash ? kTri : 1][BLOCK];
   __shared__ unsigned long long sh_stat[2 + LBM_HIST_BINS];
 
   const int tid = threadIdx.x;
@@ -547,10 +551,10 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   // source, or from this node's slot of the output buffer where rebuilt;
   // parked in LDS; moments in the frame of the node's lattice (eq. polyTemp)
   double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
+  PullMap pm;  // sources of this pull; the next pull reuses them unless the lattice changes
   if (active) {
     S fv[kQ], gv[kQ];
     if constexpr (STREAM) {
-      PullMap pm;
       pm.build(x, y, unx, uny, a.grid);
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
@@ -626,8 +630,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     // links of the next pull whose source collides in another lattice this
     // step (the source's lattice of this step is the Un half of its tag)
     if (P.shift_mode != 1) {
-      PullMap pm;
-      pm.build(x, y, nux, nuy, a.grid);
+      if (!STREAM || nux != unx || nuy != uny) pm.build(x, y, nux, nuy, a.grid);
       const int nun16 = (nux & 0xFF) | ((nuy & 0xFF) << 8);
       int st[kQ];
       static_for<0, kQ>([&](auto kc) {
@@ -641,9 +644,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     }
     if (physical) {
       // a5: numerical equilibrium
-      const NewtonOut no =
-          solve_of<M>(a.table, upx, upy, T, P, w,
-                      FactorStash{kStash ? &sh_fac[0][tid] : nullptr, BLOCK});
+      const NewtonOut no = solve_of<M>(a.table, upx, upy, T, P, w);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -661,12 +662,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
       });
     } else {
       // a6: collision, eq. (coll), with g_eq = (2 Cv - D) T f_eq (eq. gEq)
+      Weights fe;  // f_eq = rho w, shared by the sensor and the collision
+      fe.w0 = rho * w.w0;
+#pragma unroll
+      for (int p = 0; p < kPairs; ++p) {
+        fe.wp[p] = rho * w.wp[p];
+        fe.wm[p] = rho * w.wm[p];
+      }
       double tau = 0.5 + P.nu / T;
       if (P.sensor) {
         double eps = 0.0;
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          const double feq = rho * weight_of<k>(w);
+          const double feq = weight_of<k>(fe);
           // one Newton-Raphson step on the hardware reciprocal: ~1e-14 relative
           const double r0 = __builtin_amdgcn_rcp(feq);
           const double ifeq = __builtin_fma(__builtin_fma(-feq, r0, 1.0), r0, r0);
@@ -695,7 +703,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
         const double ks = om - rcp64(tpr);
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          const double feq = rho * weight_of<k>(w);
+          const double feq = weight_of<k>(fe);
           const double geq = gfac * feq;
           double sf, sg;
           shakhov_phi<plane_cx(k), plane_cy(k)>(sc, sf, sg);
@@ -709,7 +717,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
       } else
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const double feq = rho * weight_of<k>(w);
+        const double feq = weight_of<k>(fe);
         const double geq = gfac * feq;
         const S fk = sh_pop[k][tid], gk = sh_pop[kQ + k][tid];
         if constexpr (std::is_same<S, double>::value) {

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from test_gpu_parity import (TOL, check, check_fp32_sensor, gpu_run, lbm,  # noqa: F401
+from test_gpu_parity import (TOL, check, gpu_run, lbm,  # noqa: F401
                              oracle_run, shift_disagreement)
 
 pytestmark = pytest.mark.gpu
@@ -36,11 +36,8 @@ def test_parity_four_constraints(lbm, orc, name, precision):
     print(f"case {name} M=4 {precision} {wl.nx}x{wl.ny} steps {steps}", flush=True)
     _, ref = oracle_run(orc, wl, steps, constraints=4)
     _, got = gpu_run(lbm, wl, steps, precision, constraints=4)
-    if precision == "fp32" and wl.sensor:
-        check_fp32_sensor(orc, got, ref, f"{name}/M4/{precision}")
-    else:
-        check(orc, got, ref, TOL[precision], f"{name}/M4/{precision}")
-        shift_disagreement(got, ref)
+    check(orc, got, ref, TOL[precision], f"{name}/M4/{precision}")
+    shift_disagreement(got, ref)
 
 
 def test_uniform_state_stays_uniform(lbm):

@@ -2,13 +2,16 @@
 configuration, over the configurations' own horizons (the FP64 GPU form is
 the oracle's to 1e-12 on every parity case, so it stands in for the oracle
 at sizes the oracle cannot run).  Printed as a report; the asserted bounds
-are the measured levels with a margin, so that a regression shows.
+are the measured levels with a margin of about 2.5, so that a regression
+shows.
 
-FP32 rounding of the stored populations (~6e-8 per step) is not damped at
-tau close to 1/2 (the vortex runs at tau = 1/2 + 1e-4) and it is amplified
-where the Knudsen-number sensor's piecewise-constant alpha switches near
-shocks, so the error grows with the horizon: the 1e-5 bound holds over the
-short horizons of the parity tests, not over thousands of steps."""
+FP32 rounding of the stored populations (~6e-8 per step) is amplified by
+the flows themselves (shocks, and tau close to 1/2 in the vortex): the
+same dynamics take a one-ulp FP64 perturbation of the oracle's input to
+8e-7 over the advected Sod's 2000 steps (tests/golden/sensitivity.json).
+So the error grows with the horizon: the 1e-5 max-norm bound holds over
+the parity tests' horizons (<= 200 steps), not over thousands of steps,
+where these are the form's stated errors."""
 import numpy as np
 import pytest
 
@@ -18,10 +21,10 @@ pytestmark = pytest.mark.gpu
 
 CASES = {
     # name: (workload, steps, bound on the max error, bound on the L1 error)
-    "C0_sod_256x1": (lambda: W.config0(), 200, 1e-5, 1e-6),
-    "C1_advected_sod_2048x4": (lambda: W.config1(2048, 4, 2000), 2000, 2e-1, 3e-3),
-    "C2_vortex_1024": (lambda: W.config2(1024, 5000), 5000, 3e-2, 3e-3),
-    "C3_quadrant_4096": (lambda: W.config3(4096, 1000), 1000, 2e-1, 3e-3),
+    "C0_sod_256x1": (lambda: W.config0(), 200, 5e-6, 3e-7),
+    "C1_advected_sod_2048x4": (lambda: W.config1(2048, 4, 2000), 2000, 1.2e-2, 4e-4),
+    "C2_vortex_1024": (lambda: W.config2(1024, 5000), 5000, 7e-3, 4e-4),
+    "C3_quadrant_4096": (lambda: W.config3(4096, 1000), 1000, 2.4e-1, 7e-4),
 }
 
 

@@ -1,16 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle on the same
 seeded inputs.  Metrics (relative): rho and T max_n |a - b| / |b|; velocity
 max_n |u_a - u_b| / max_n |u_b|.  FP64 form: 1e-12.  FP32 storage form:
-1e-5 (the bound stated for the FP32-storage / FP64-Newton form).
-
-The Knudsen-number sensor (eq. DeltaAvg) scales tau by a piecewise-constant
-alpha.  Near a shock, FP32 rounding of the stored populations (~6e-8 per
-step) can put a node's eps on the other side of one of alpha's steps than
-the FP64 oracle's; tau then differs by 5-35 % at that node for a step and
-the node's state by up to ~1e-4.  For FP32 runs with the sensor on, the
-1e-5 bound therefore applies to the relative L1 error over the field
-(sum |a - b| / sum |b|), and the maximum is held to 1e-3; the max-norm
-bound of 1e-5 is checked on FP32 runs without the sensor."""
+1e-5 (the bound stated for the FP32-storage / FP64-Newton form), max-norm
+over every node, with the Knudsen-number sensor on or off (its alpha is
+continuous, so FP32 rounding of eps moves tau by a rounding-level
+amount)."""
 import numpy as np
 import pytest
 
@@ -19,7 +13,6 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
-FP32_SENSOR_MAX = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -63,26 +56,6 @@ def check(orc, got, ref, tol, what):
     print(f"{what}: rel err rho {e['rho']:.2e} u {e['u']:.2e} T {e['T']:.2e}", flush=True)
     assert max(e.values()) <= tol, (what, e)
     return e
-
-
-def l1_errors(got, ref):
-    out = {}
-    for k in ("rho", "T"):
-        out[k] = float(np.sum(np.abs(got[k] - ref[k])) / np.sum(np.abs(ref[k])))
-    num = np.sum(np.hypot(got["ux"] - ref["ux"], got["uy"] - ref["uy"]))
-    out["u"] = float(num / np.sum(np.hypot(ref["ux"], ref["uy"])))
-    return out
-
-
-def check_fp32_sensor(orc, got, ref, what):
-    """FP32 form with the sensor on: L1 within the FP32 bound, maximum within
-    the bound of a sensor step taken differently (module docstring)."""
-    e = errors(orc, got, ref)
-    l1 = l1_errors(got, ref)
-    print(f"{what}: max rel err rho {e['rho']:.2e} u {e['u']:.2e} T {e['T']:.2e}; "
-          f"L1 rho {l1['rho']:.2e} u {l1['u']:.2e} T {l1['T']:.2e}", flush=True)
-    assert max(l1.values()) <= TOL["fp32"], (what, l1)
-    assert max(e.values()) <= FP32_SENSOR_MAX, (what, e)
 
 
 def shift_disagreement(got, ref, tie_width=1e-9):
@@ -134,11 +107,8 @@ def test_parity_small(lbm, orc, name, precision):
     print(f"case {name} {precision} {wl.nx}x{wl.ny} steps {steps}", flush=True)
     _, ref = oracle_run(orc, wl, steps)
     _, got = gpu_run(lbm, wl, steps, precision)
-    if precision == "fp32" and wl.sensor:
-        check_fp32_sensor(orc, got, ref, f"{name}/{precision}")
-    else:
-        check(orc, got, ref, TOL[precision], f"{name}/{precision}")
-        shift_disagreement(got, ref)
+    check(orc, got, ref, TOL[precision], f"{name}/{precision}")
+    shift_disagreement(got, ref)
 
 
 def test_parity_populations_fp64(lbm, orc):

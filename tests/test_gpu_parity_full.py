@@ -4,8 +4,8 @@ periodic crops centred on sampled nodes, wide enough that the crop's seam
 cannot reach the centre within the steps taken (a node's state after s steps
 depends on nodes at most s * (3 + |U| + 1) away: pull reach plus the
 central-difference stencil of a rebuilt link), and the centre nodes are
-compared.  Bounds as in test_gpu_parity (FP64 1e-12; FP32 1e-5, or with the
-sensor on 1e-3 per node and 1e-5 on the median)."""
+compared.  Bounds as in test_gpu_parity (FP64 1e-12; FP32 1e-5, max-norm,
+with the Knudsen-number sensor on)."""
 import numpy as np
 import pytest
 
@@ -76,7 +76,7 @@ def oracle_values(orc, wl, steps, pts, **over):
     return {k: np.array(v) for k, v in out.items()}
 
 
-def compare(got, ref, precision, sensor, what, fp64_bounds=(1e-12, 1e-12)):
+def compare(got, ref, precision, what, fp64_bounds=(1e-12, 1e-12), fp32_bound=1e-5):
     u_scale = np.max(np.hypot(ref["ux"], ref["uy"]))
     e = np.maximum.reduce([np.abs(got["rho"] - ref["rho"]) / np.abs(ref["rho"]),
                            np.abs(got["T"] - ref["T"]) / np.abs(ref["T"]),
@@ -84,10 +84,9 @@ def compare(got, ref, precision, sensor, what, fp64_bounds=(1e-12, 1e-12)):
     print(f"{what}: per-node max rel err {e.max():.2e}, median {np.median(e):.2e}", flush=True)
     if precision == "fp64":
         assert e.max() <= fp64_bounds[0] and np.median(e) <= fp64_bounds[1], (what, e.max())
-    elif sensor:
-        assert e.max() <= 1e-3 and np.median(e) <= 1e-5, (what, e.max(), np.median(e))
     else:
-        assert e.max() <= 1e-5, (what, e.max())
+        assert e.max() <= fp32_bound, (what, e.max())
+    return e
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
@@ -98,7 +97,7 @@ def test_quadrant_4096_sampled(lbm, orc, precision):
     print(f"quadrant 4096^2 {precision}, {steps} steps, {len(pts)} sampled nodes", flush=True)
     got = gpu_values(lbm, wl, steps, precision, pts)
     ref = oracle_values(orc, wl, steps, pts)
-    compare(got, ref, precision, wl.sensor, f"quadrant_4096/{precision}")
+    compare(got, ref, precision, f"quadrant_4096/{precision}")
 
 
 # the variants bench.py times on the same draw: (precision, options, steps,
@@ -120,7 +119,7 @@ def test_quadrant_4096_variants_sampled(lbm, orc, name):
     print(f"quadrant 4096^2 {name}, {steps} steps, {len(pts)} sampled nodes", flush=True)
     got = gpu_values(lbm, wl, steps, precision, pts, **over)
     ref = oracle_values(orc, wl, steps, pts, **over)
-    compare(got, ref, precision, wl.sensor, f"quadrant_4096/{name}")
+    compare(got, ref, precision, f"quadrant_4096/{name}")
 
 
 def test_quadrant_16384_fp64_planes_above_2gib(lbm, orc):
@@ -143,7 +142,7 @@ def test_quadrant_16384_fp64_planes_above_2gib(lbm, orc):
     print(f"quadrant 16384^2 fp64, {steps} steps, {len(pts)} sampled nodes", flush=True)
     got = gpu_values(lbm, wl, steps, "fp64", pts)
     ref = oracle_values(orc, wl, steps, pts)
-    compare(got, ref, "fp64", wl.sensor, "quadrant_16384/fp64")
+    compare(got, ref, "fp64", "quadrant_16384/fp64")
 
 
 _VORTEX_REF = {}
@@ -154,7 +153,6 @@ def _vortex_oracle(orc, steps, c, half):
     key = (steps, c, half)
     if key not in _VORTEX_REF:
         wl = W.config2(1024, steps)
-        wl.sensor = 0
         s = orc.Sim.from_workload(wl.window(c, c, half))
         s.step(steps)
         _VORTEX_REF[key] = s.macros()
@@ -169,8 +167,7 @@ def test_vortex_1024_block(lbm, orc, precision):
     block that the seam cannot reach within the steps taken is compared."""
     import torch
     steps = 10
-    wl = W.config2(1024, steps)
-    wl.sensor = 0          # smooth flow over 10 steps: the strict FP32 bound applies
+    wl = W.config2(1024, steps)    # Knudsen sensor on, as in the configuration
     c, half = 512, 320
     inner = half - steps * REACH - 8
     print(f"vortex 1024^2 {precision}, {steps} steps, block of {(2 * inner + 1) ** 2} nodes", flush=True)
@@ -186,38 +183,87 @@ def test_vortex_1024_block(lbm, orc, precision):
     isl = slice(half - inner, half + inner + 1)
     ref = {k: rm[k][isl, isl] for k in ("rho", "ux", "uy", "T")}
     compare({k: v.ravel() for k, v in got.items()}, {k: v.ravel() for k, v in ref.items()},
-            precision, wl.sensor, f"vortex_1024/{precision}")
+            precision, f"vortex_1024/{precision}")
 
 
-_C1_REF = {}
+def _sensitivity(name, steps):
+    """The oracle's own drift at `steps` when its input moves by one ulp
+    (tests/golden/make_sensitivity.py): (max, median) over nodes."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "sensitivity.json")
+    rows = json.load(open(path))[name]
+    r = next(r for r in rows if r["steps"] == steps)
+    return r["max"], r["median"]
 
 
-@pytest.mark.parametrize("precision", ["fp64"])
-def test_advected_sod_2048x4_full(lbm, orc, precision):
-    """The whole 2048 x 4 grid after the configuration's 2000 steps, against
-    the oracle run on the same grid (shocks, lattice changes and the sensor
-    throughout; the FP32 form's error over this horizon is reported by
-    test_gpu_fp32_report).  Over this
-    horizon the shocks amplify the rounding differences of the two sides
-    (summation order, Newton paths) from ~1e-16 to ~3e-10 at the shocks
-    and ~1e-12 elsewhere, so the FP64 form is held to 1e-9 per node and
-    1e-11 on the median; over the 150-step horizon of test_gpu_parity the
-    1e-12 bound holds on every node."""
-    steps = 2000
-    wl = W.config1(2048, 4, steps)
-    if steps not in _C1_REF:
-        s = orc.Sim.from_workload(wl)
-        s.step(steps)
-        _C1_REF[steps] = s.macros()
-    ref = _C1_REF[steps]
+def test_advected_sod_2048x4_full(lbm, orc):
+    """The whole 2048 x 4 grid (shocks, lattice changes and the sensor
+    throughout) against the oracle run on the same grid, FP64.  Up to step
+    500 every node is within 1e-12.  Later the flow amplifies rounding
+    differences: the oracle itself, with its initial density moved by one
+    ulp, drifts to ~1e-12 by step 750 and ~8e-7 (median ~3e-10) by step
+    2000 (tests/golden/sensitivity.json), so two FP64 implementations that
+    round differently cannot agree to 1e-12 there; at the configuration's
+    2000 steps the GPU is held to four times the oracle's own one-ulp drift
+    (max and median).  The FP32 form's error over this horizon is reported
+    by test_gpu_fp32_report."""
+    wl = W.config1(2048, 4, 2000)
+    o = orc.Sim.from_workload(wl)
+    sim = lbm.Sim.from_workload(wl, precision="fp64")
+    done = 0
+    for steps in (500, 2000):
+        o.step(steps - done)
+        sim.step(steps - done)
+        done = steps
+        ref = o.macros()
+        got = {k: v.cpu().numpy() for k, v in sim.macros().items()}
+        keys = ("rho", "ux", "uy", "T")
+        if steps == 500:
+            compare({k: got[k].ravel() for k in keys}, {k: ref[k].ravel() for k in keys},
+                    "fp64", f"advected_sod_2048x4/fp64/{steps}")
+        else:
+            mx, med = _sensitivity("advected_sod_2048x4", steps)
+            print(f"oracle one-ulp drift at {steps}: max {mx:.2e} median {med:.2e}", flush=True)
+            compare({k: got[k].ravel() for k in keys}, {k: ref[k].ravel() for k in keys},
+                    "fp64", f"advected_sod_2048x4/fp64/{steps}",
+                    fp64_bounds=(4 * mx, 4 * med))
+    sim.close()
+
+
+# FP32-storage error against the oracle at the vortex copy's full horizon:
+# the measured 2.7e-5 with a margin of about 2.5 (the form's stated error
+# for this configuration)
+VORTEX_FP32_BOUND = 7e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vortex_256_full_horizon(lbm, precision):
+    """The isentropic vortex's quarter-size copy (256^2, 1250 steps: the
+    same number of vortex transits as the 1024^2, 5000-step configuration;
+    sensor on, tau = 1/2 + 1e-4) on the GPU, against sampled rows of the
+    oracle's run stored by tests/golden/make_vortex_golden.py.  FP64: within
+    1e-12, or four times the oracle's own one-ulp drift at this horizon
+    where that is larger (tests/golden/sensitivity.json).  FP32 storage:
+    the stated error of the form for this configuration."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "vortex_256_1250.npz"),
+                allow_pickle=False)
+    L, steps, rows = int(g["L"]), int(g["steps"]), g["rows"]
+    wl = W.config2(L, steps)
     sim = lbm.Sim.from_workload(wl, precision=precision)
     sim.step(steps)
-    got = {k: v.cpu().numpy() for k, v in sim.macros().items()}
+    m = sim.macros()
+    got = {k: m[k].cpu().numpy()[rows].ravel() for k in ("rho", "ux", "uy", "T")}
     sim.close()
-    compare({k: got[k].ravel() for k in ("rho", "ux", "uy", "T")},
-            {k: ref[k].ravel() for k in ("rho", "ux", "uy", "T")},
-            precision, wl.sensor, f"advected_sod_2048x4/{precision}/{steps}",
-            fp64_bounds=(1e-9, 1e-11))
+    ref = {k: g[k].ravel() for k in ("rho", "ux", "uy", "T")}
+    if precision == "fp64":
+        mx, med = _sensitivity("vortex_256", steps)
+        print(f"oracle one-ulp drift at {steps}: max {mx:.2e} median {med:.2e}", flush=True)
+        compare(got, ref, "fp64", f"vortex_256/fp64/{steps}",
+                fp64_bounds=(max(1e-12, 4 * mx), max(1e-12, 4 * med)))
+    else:
+        compare(got, ref, "fp32", f"vortex_256/fp32/{steps}", fp32_bound=VORTEX_FP32_BOUND)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])

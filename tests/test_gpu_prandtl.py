@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from test_gpu_parity import (TOL, check, check_fp32_sensor, gpu_run, lbm,  # noqa: F401
+from test_gpu_parity import (TOL, check, gpu_run, lbm,  # noqa: F401
                              oracle_run, shift_disagreement)
 
 pytestmark = pytest.mark.gpu
@@ -38,11 +38,8 @@ def test_parity_prandtl(lbm, orc, name, precision, Pr):
     print(f"case {name} Pr={Pr} {precision} {wl.nx}x{wl.ny} steps {steps}", flush=True)
     _, ref = oracle_run(orc, wl, steps, prandtl=Pr)
     sim, got = gpu_run(lbm, wl, steps, precision, prandtl=Pr)
-    if precision == "fp32" and wl.sensor:
-        check_fp32_sensor(orc, got, ref, f"{name}/Pr{Pr}/{precision}")
-    else:
-        check(orc, got, ref, TOL[precision], f"{name}/Pr{Pr}/{precision}")
-        shift_disagreement(got, ref)
+    check(orc, got, ref, TOL[precision], f"{name}/Pr{Pr}/{precision}")
+    shift_disagreement(got, ref)
     sim.close()
 
 

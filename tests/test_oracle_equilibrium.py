@@ -35,6 +35,19 @@ STATES = [(0.0, 0.0, 0.7), (0.3, -0.2, 0.7), (0.5, 0.5, 0.5), (-0.45, 0.1, 1.4),
           (1.2, 0.0, 0.7), (0.9, -0.8, 1.0), (1.5, 0.0, 0.5), (0.0, -1.5, 1.4)]
 
 
+def maxwellian_moments8(ux, uy, T, n=8):
+    """E[phi(xi)] of the eight monomials of eq. (feqNum_8Mom) for xi ~ N(u, T I),
+    the continuous Maxwellian per unit density, by a tensor Gauss-Hermite
+    rule of n points per axis (exact for polynomials of degree < 2n): the
+    quantities the constraints of App. C make the lattice reproduce, taken
+    without any closed form."""
+    z, wz = np.polynomial.hermite_e.hermegauss(n)
+    Z1, Z2 = np.meshgrid(z, z, indexing="ij")
+    W2 = (np.outer(wz, wz) / (2 * math.pi)).ravel()
+    c = np.stack([ux + math.sqrt(T) * Z1.ravel(), uy + math.sqrt(T) * Z2.ravel()], 1)
+    return paper_basis(c).T @ W2
+
+
 def test_lattice_is_d2q21_reading(orc):
     v = orc.velocities()
     assert v.shape == (21, 2)
@@ -196,3 +209,26 @@ def test_nonphysical_inputs_are_rejected(orc):
 def test_targets_match_paper(orc):
     for s in STATES:
         assert np.allclose(orc.targets(*s), paper_targets(*s), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES)
+def test_targets_are_maxwellian_moments(orc, ux, uy, T):
+    """The eight targets of eqs. (G0_8mom)-(G3yaa_8mom) are the moments of the
+    continuous Maxwellian: checked against Gauss-Hermite quadrature of the
+    monomials themselves (a dropped term, e.g. the 4T of the heat-flux
+    targets, or a wrong sign fails here)."""
+    m = orc.targets(ux, uy, T)
+    ref = maxwellian_moments8(ux, uy, T)
+    assert np.max(np.abs(m - ref) / np.maximum(np.abs(ref), 1.0)) < 1e-13
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES)
+def test_equilibrium_reproduces_maxwellian_moments(orc, ux, uy, T):
+    """The lattice equilibrium's eight moments equal the quadrature moments of
+    the continuous Maxwellian to rounding (the paper's 1e-12 criterion
+    leaves about 1e-14, App. C)."""
+    w, lam, it, rc = orc.equilibrium(ux, uy, T)
+    assert rc == 0
+    ref = maxwellian_moments8(ux, uy, T)
+    got = paper_basis(orc.velocities()).T @ w
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)) < 1e-13

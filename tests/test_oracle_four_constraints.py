@@ -28,6 +28,29 @@ STATES = [(0.0, 0.0, 0.7), (0.3, -0.2, 0.7), (0.5, 0.5, 0.5), (-0.45, 0.1, 1.4),
           (1.0, 0.0, 0.7), (0.7, -0.6, 1.0)]
 
 
+def maxwellian_moments4(ux, uy, T, n=6):
+    """E[(1, xi_x, xi_y, |xi|^2)] for xi ~ N(u, T I) by a tensor Gauss-Hermite
+    rule (exact for these degrees): mass, momentum and twice the total
+    energy of the continuous Maxwellian per unit density, without any
+    closed form."""
+    z, wz = np.polynomial.hermite_e.hermegauss(n)
+    Z1, Z2 = np.meshgrid(z, z, indexing="ij")
+    W2 = (np.outer(wz, wz) / (2 * math.pi)).ravel()
+    c = np.stack([ux + math.sqrt(T) * Z1.ravel(), uy + math.sqrt(T) * Z2.ravel()], 1)
+    return basis4(c).T @ W2
+
+
+@pytest.mark.parametrize("ux,uy,T", STATES)
+def test_four_targets_are_maxwellian_moments(orc, ux, uy, T):
+    ref = maxwellian_moments4(ux, uy, T)
+    m = orc.targets_m(4, ux, uy, T)
+    assert np.max(np.abs(m - ref) / np.maximum(np.abs(ref), 1.0)) < 1e-13
+    w, lam, it, rc = orc.equilibrium(ux, uy, T, constraints=4)
+    assert rc == 0
+    got = basis4(orc.velocities()).T @ w
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)) < 1e-13
+
+
 @pytest.mark.parametrize("ux,uy,T", STATES)
 def test_four_constraints_reproduced(orc, ux, uy, T):
     w, lam, it, rc = orc.equilibrium(ux, uy, T, constraints=4)
