@@ -256,6 +256,19 @@ lbm_status lbm_get_diag(lbm_ctx* ctx, lbm_diag* out);
  * which). */
 lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): lbm_step_batched with
+ * the same arguments, results and errors, except that the job table and the
+ * failure words live in a library-owned device array of fixed size (up to
+ * 1024 contexts, about 260 KB; every device the library runs on holds its
+ * own copy until the process ends) instead of ctxs[0]'s workspace.  Calls
+ * no hipMalloc, hipFree or other allocating routine.  The current device
+ * must be the contexts' device (else LBM_ERR_ARG); n > 1024 gives
+ * LBM_ERR_ARG.  All calls on one device share that array, so calls that
+ * overlap on one device (other streams or threads) race; the host-side
+ * staging is shared by the process, and calls are serialised on it. */
+lbm_status lbm_step_batched_noalloc(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n);
+
 /* Frees the host context; the workspace stays the caller's. */
 void lbm_destroy(lbm_ctx* ctx);
 

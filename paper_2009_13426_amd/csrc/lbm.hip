@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -565,6 +566,130 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
   return st;
 }
 
+// One rebuild launch and one step launch per step for every context of a
+// batch.  dev_jobs / dev_keys: device memory for the job table and the
+// failure words (n entries each); host_jobs / host_keys: host staging of
+// the same size.
+lbm_status step_batched_common(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n,
+                               JobArgs* dev_jobs, unsigned long long* dev_keys,
+                               JobArgs* host_jobs, unsigned long long* host_keys) {
+  int32_t most = 0;
+  bool any_rebuild = false;
+  long long nodes = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    lbm_ctx* c = ctxs[k];
+    if (!c || nsteps[k] < 0) return LBM_ERR_ARG;
+    if (c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD || c->cfg.constraints == kM13 ||
+        shakhov_on(&c->cfg))
+      return LBM_ERR_ARG;
+    if (c->cfg.precision != ctxs[0]->cfg.precision ||
+        c->cfg.constraints != ctxs[0]->cfg.constraints || c->stream != ctxs[0]->stream ||
+        c->device != ctxs[0]->device)
+      return LBM_ERR_ARG;
+    for (int32_t m = 0; m < k; ++m)
+      if (ctxs[m] == c) return LBM_ERR_ARG;
+    if (!c->initialized) return LBM_ERR_STATE;
+    most = std::max(most, nsteps[k]);
+    any_rebuild = any_rebuild || c->cfg.shift_mode != LBM_SHIFT_FIXED;
+    nodes += c->grid.N;
+  }
+  // job table, blocks of the step launch in job order
+  const int B = ctxs[0]->sched.step_block;
+  const void* step_fn = step_batched_fn(ctxs[0]->cfg.precision, B, ctxs[0]->cfg.constraints);
+  if (!step_fn) return LBM_ERR_ARG;
+  long long blocks = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    lbm_ctx* c = ctxs[k];
+    JobArgs& j = host_jobs[k];
+    for (int b = 0; b < 2; ++b) {
+      j.pop[b] = c->f(b);
+      j.tag[b] = c->tag(b);
+    }
+    j.carry = c->carry();
+    j.grid = c->grid;
+    j.phys = c->phys;
+    j.table = c->table;
+    j.diag = c->diag();
+    j.cur = c->cur;
+    j.step0 = static_cast<int>(c->steps_done);
+    j.nsteps = nsteps[k];
+    j.block0 = static_cast<int>(blocks);
+    j.nblocks = static_cast<int>((c->grid.N + B - 1) / B);
+    blocks += j.nblocks;
+  }
+  if (blocks >= (1ll << 31)) return LBM_ERR_ARG;
+  lbm_ctx* c0 = ctxs[0];
+  HIP_TRY(hipMemcpyAsync(dev_jobs, host_jobs, n * sizeof(JobArgs), hipMemcpyHostToDevice,
+                         c0->stream));
+  const dim3 step_grid(static_cast<unsigned>(blocks));
+  const dim3 rebuild_grid(static_cast<unsigned>(std::min<long long>((nodes + kBlock - 1) / kBlock, 4096)));
+  const void* rebuild_batched = rebuild_batched_fn(c0->cfg.precision, c0->cfg.constraints);
+  int remap = c0->sched.xcd_remap;
+  for (int32_t st = 0; st < most; ++st) {
+    int njobs = n, s_arg = st;
+    void* rebuild_params[] = {&dev_jobs, &njobs, &s_arg};
+    void* step_params[] = {&dev_jobs, &njobs, &s_arg, &remap};
+    if (any_rebuild)
+      HIP_TRY(hipLaunchKernel(rebuild_batched, rebuild_grid, dim3(kBlock), rebuild_params, 0,
+                              c0->stream));
+    HIP_TRY(hipLaunchKernel(step_fn, step_grid, dim3(B), step_params, 0, c0->stream));
+    HIP_TRY(hipGetLastError());
+  }
+  for (int32_t k = 0; k < n; ++k) {
+    ctxs[k]->cur ^= (nsteps[k] & 1);
+    ctxs[k]->steps_done += nsteps[k];
+  }
+  // every job's failure word in one copy
+  hipLaunchKernelGGL(gather_fail_keys_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     c0->stream, dev_jobs, n, dev_keys);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(host_keys, dev_keys, n * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, c0->stream));
+  HIP_TRY(hipStreamSynchronize(c0->stream));
+  for (int32_t k = 0; k < n; ++k)
+    if (host_keys[k] != ~0ull)
+      return (host_keys[k] & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
+  return LBM_OK;
+}
+
+// ------------------------------------------------- allocation-free batches
+// lbm_step_batched_noalloc keeps its job table and failure words in this
+// file-scope device array instead of the first context's workspace; every
+// device the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: the device address
+// of each device's copy comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+constexpr size_t kScratchJobsBytes =
+    (kMaxBatch * sizeof(JobArgs) + 255) / 256 * 256;
+constexpr size_t kScratchBytes = kScratchJobsBytes + kMaxBatch * sizeof(unsigned long long);
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// host staging of the allocation-free batch (one batch at a time per process)
+std::mutex g_noalloc_host_mu;
+JobArgs g_noalloc_host_jobs[kMaxBatch];
+unsigned long long g_noalloc_host_keys[kMaxBatch];
+
+lbm_status scratch_of_device(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return LBM_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return LBM_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -943,89 +1068,31 @@ lbm_status lbm_get_diag(lbm_ctx* c, lbm_diag* out) {
 }
 
 lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n) {
-  if (!ctxs || !nsteps || n < 0 || n > kMaxBatch) return LBM_ERR_ARG;
+  if (!ctxs || !nsteps || n < 0 || n > kMaxBatch || (n > 0 && !ctxs[0])) return LBM_ERR_ARG;
   if (n == 0) return LBM_OK;
-  int32_t most = 0;
-  bool any_rebuild = false;
-  long long nodes = 0;
-  for (int32_t k = 0; k < n; ++k) {
-    lbm_ctx* c = ctxs[k];
-    if (!c || nsteps[k] < 0) return LBM_ERR_ARG;
-    if (c->cfg.shift_mode == LBM_SHIFT_NEIGHBOURHOOD || c->cfg.constraints == kM13 ||
-        shakhov_on(&c->cfg))
-      return LBM_ERR_ARG;
-    if (c->cfg.precision != ctxs[0]->cfg.precision ||
-        c->cfg.constraints != ctxs[0]->cfg.constraints || c->stream != ctxs[0]->stream ||
-        c->device != ctxs[0]->device)
-      return LBM_ERR_ARG;
-    for (int32_t m = 0; m < k; ++m)
-      if (ctxs[m] == c) return LBM_ERR_ARG;
-    if (!c->initialized) return LBM_ERR_STATE;
-    most = std::max(most, nsteps[k]);
-    any_rebuild = any_rebuild || c->cfg.shift_mode != LBM_SHIFT_FIXED;
-    nodes += c->grid.N;
-  }
-  // job table, blocks of the step launch in job order
-  const int B = ctxs[0]->sched.step_block;
-  const void* step_fn = step_batched_fn(ctxs[0]->cfg.precision, B, ctxs[0]->cfg.constraints);
-  if (!step_fn) return LBM_ERR_ARG;
   std::vector<JobArgs> jobs(n);
-  long long blocks = 0;
-  for (int32_t k = 0; k < n; ++k) {
-    lbm_ctx* c = ctxs[k];
-    JobArgs& j = jobs[k];
-    for (int b = 0; b < 2; ++b) {
-      j.pop[b] = c->f(b);
-      j.tag[b] = c->tag(b);
-    }
-    j.carry = c->carry();
-    j.grid = c->grid;
-    j.phys = c->phys;
-    j.table = c->table;
-    j.diag = c->diag();
-    j.cur = c->cur;
-    j.step0 = static_cast<int>(c->steps_done);
-    j.nsteps = nsteps[k];
-    j.block0 = static_cast<int>(blocks);
-    j.nblocks = static_cast<int>((c->grid.N + B - 1) / B);
-    blocks += j.nblocks;
-  }
-  if (blocks >= (1ll << 31)) return LBM_ERR_ARG;
-  lbm_ctx* c0 = ctxs[0];
-  JobArgs* dev_jobs = reinterpret_cast<JobArgs*>(c0->ws + c0->lay.batch_off);
-  HIP_TRY(hipMemcpyAsync(dev_jobs, jobs.data(), n * sizeof(JobArgs), hipMemcpyHostToDevice,
-                         c0->stream));
-  const dim3 step_grid(static_cast<unsigned>(blocks));
-  const dim3 rebuild_grid(static_cast<unsigned>(std::min<long long>((nodes + kBlock - 1) / kBlock, 4096)));
-  const void* rebuild_batched = rebuild_batched_fn(c0->cfg.precision, c0->cfg.constraints);
-  int remap = c0->sched.xcd_remap;
-  for (int32_t st = 0; st < most; ++st) {
-    int njobs = n, s_arg = st;
-    void* rebuild_params[] = {&dev_jobs, &njobs, &s_arg};
-    void* step_params[] = {&dev_jobs, &njobs, &s_arg, &remap};
-    if (any_rebuild)
-      HIP_TRY(hipLaunchKernel(rebuild_batched, rebuild_grid, dim3(kBlock), rebuild_params, 0,
-                              c0->stream));
-    HIP_TRY(hipLaunchKernel(step_fn, step_grid, dim3(B), step_params, 0, c0->stream));
-    HIP_TRY(hipGetLastError());
-  }
-  for (int32_t k = 0; k < n; ++k) {
-    ctxs[k]->cur ^= (nsteps[k] & 1);
-    ctxs[k]->steps_done += nsteps[k];
-  }
-  // every job's failure word in one copy
-  unsigned long long* dev_keys = reinterpret_cast<unsigned long long*>(c0->ws + c0->lay.keys_off);
-  hipLaunchKernelGGL(gather_fail_keys_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0,
-                     c0->stream, dev_jobs, n, dev_keys);
-  HIP_TRY(hipGetLastError());
   std::vector<unsigned long long> keys(n, ~0ull);
-  HIP_TRY(hipMemcpyAsync(keys.data(), dev_keys, n * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, c0->stream));
-  HIP_TRY(hipStreamSynchronize(c0->stream));
-  for (int32_t k = 0; k < n; ++k)
-    if (keys[k] != ~0ull)
-      return (keys[k] & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
-  return LBM_OK;
+  lbm_ctx* c0 = ctxs[0];
+  return step_batched_common(ctxs, nsteps, n,
+                             reinterpret_cast<JobArgs*>(c0->ws + c0->lay.batch_off),
+                             reinterpret_cast<unsigned long long*>(c0->ws + c0->lay.keys_off),
+                             jobs.data(), keys.data());
+}
+
+lbm_status lbm_step_batched_noalloc(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n) {
+  if (!ctxs || !nsteps || n < 0 || n > kMaxBatch || (n > 0 && !ctxs[0])) return LBM_ERR_ARG;
+  if (n == 0) return LBM_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBM_ERR_HIP;
+  if (dev != ctxs[0]->device) return LBM_ERR_ARG;
+  char* sp = nullptr;
+  const lbm_status st = scratch_of_device(dev, &sp);
+  if (st) return st;
+  // one batch at a time per process: the host staging below is shared
+  std::lock_guard<std::mutex> lock(g_noalloc_host_mu);
+  return step_batched_common(ctxs, nsteps, n, reinterpret_cast<JobArgs*>(sp),
+                             reinterpret_cast<unsigned long long*>(sp + kScratchJobsBytes),
+                             g_noalloc_host_jobs, g_noalloc_host_keys);
 }
 
 void lbm_destroy(lbm_ctx* c) { delete c; }
