@@ -15,20 +15,25 @@ Newton); the FP64 form is timed the same way and reported beside it.
 One JSON line on stdout.  Inputs are resident on the GPU before timing
 starts.  The launch schedule is the autotuner's choice for the grid's size
 class (tuned and cached before any timing on a miss; --schedule default
-keeps the library's).  The timed region is K steps between two
-synchronisations, replayed as HIP graphs of --graph-chunk steps; a second
-pass of K steps with HIP events around every launch on the stream the
-library launches on gives the step kernel's and the link-rebuild kernel's
-own durations.
+keeps the library's).  Before timing, --settle plain steps (default 200)
+carry the draw into its developed state, and warm-up replays of the HIP
+graph (at least one chunk) build the graph the timed region replays.  The
+timed region is K steps between two synchronisations, replayed as HIP
+graphs of --graph-chunk steps; a second pass of K steps with HIP events
+around every launch on the stream the library launches on gives the step
+kernel's and the link-rebuild kernel's own durations.
 
-The step kernel is bound by FP64 vector arithmetic (the Newton solve), so
-`roofline` is the ALU one: FP64 flops per node update (counted by rocprofv3
-for this kernel on this workload, read from the committed summary in
-profiles/) times the nodes of one launch, over the kernel's event-timed
-duration, against the FP64 vector peak.  Its `traffic` is the HBM bytes one
-launch moves (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), reported
-only while the summary was taken on the current kernel sources; `hbm` gives
-the algorithmic-byte rate against the 8 TB/s peak.
+`roofline` is the HBM one, the target the step kernel is measured against:
+the algorithmic bytes of a node update (read and write 2 x 21 populations:
+336 B in FP32 storage, 672 B in FP64) times the nodes of one launch, over
+the step kernel's event-timed duration, against 8 TB/s and against the
+measured ceiling of the library's own streaming copy kernel.  Its `traffic`
+is the HBM bytes one launch moves (FETCH_SIZE + WRITE_SIZE, calibrated on
+a copy), reported only while the committed profile summary was taken on
+the current kernel sources.  The kernel spends most of its time in FP64
+Newton arithmetic, so `roofline.alu` gives beside it the FP64 flops and
+VALU instructions per node (from the same summary), the achieved FP64 rate
+against the 78.6 TFLOP/s vector peak and the VALU issue fraction.
 """
 import argparse
 import json
@@ -59,6 +64,15 @@ def bytes_per_node(precision):
     return 2 * 2 * Q * es + 2 * 4 + 2 * 4 + 4 * es
 
 
+def algorithmic_bytes(precision):
+    """Bytes per node update the method must move (read and write the 2 x 21
+    populations), the per-node figure the HBM roofline is taken on: 336 in
+    FP32 storage, 672 in FP64."""
+    if precision == "ref49":
+        return 2 * 2 * 49 * 8
+    return 2 * 2 * Q * (8 if precision == "fp64" else 4)
+
+
 def kernel_sources_digest():
     """sha256 over the HIP sources (the counter figures in the profile are
     valid only for the kernels they were taken on)."""
@@ -87,18 +101,22 @@ def profile_figures():
     return out
 
 
-def time_form(lbm, torch, wl, precision, steps, warmup, schedule=None, chunk=10, **over):
-    """Timed region: `steps` steps between two synchronisations, run as
-    replays of a HIP graph of `chunk` steps (lbm_step_graph_async; the graph
-    is built during the warm-up).  A second pass of `steps` steps with HIP
-    events around every launch on the library's stream gives the step and
-    link-rebuild kernels' own durations."""
+def time_form(lbm, torch, wl, precision, steps, warmup, schedule=None, chunk=10, settle=0,
+              **over):
+    """Untimed: `settle` plain steps that carry the draw into its developed
+    state (more shift interfaces, hence more rebuilt links, than the first
+    steps), then warm-up replays of a HIP graph of `chunk` steps, at least one
+    chunk, so that the graph the timed region replays is built before it.
+    Timed region: `steps` steps between two synchronisations, as replays of
+    that graph (plus plain launches for a remainder).  A second pass of
+    `steps` steps with HIP events around every launch on the library's stream
+    gives the step and link-rebuild kernels' own durations."""
     sim = lbm.Sim.from_workload(wl, precision=precision, schedule=schedule, **over)
     sched = sim.schedule
-    graphed = warmup - warmup % chunk
-    if graphed:
-        sim.step_graph(graphed, chunk)
-    sim.step(warmup - graphed)
+    if settle:
+        sim.step(settle)
+    graph_warm = max(chunk, warmup + (-warmup) % chunk)
+    sim.step_graph(graph_warm, chunk)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step_graph_async(steps, chunk)
@@ -110,42 +128,80 @@ def time_form(lbm, torch, wl, precision, steps, warmup, schedule=None, chunk=10,
     nodes = wl.nx * wl.ny
     out = dict(ms_per_step=wall * 1e3 / steps, kernel_ms=ms_step / steps,
                rebuild_ms=ms_rebuild / steps, mlups=nodes * steps / wall / 1e6,
-               conserved=d["conserved"], status=d["status"], schedule=sched)
+               conserved=d["conserved"], status=d["status"], schedule=sched,
+               untimed_steps=settle + graph_warm)
     sim.close()
     return out
 
 
-def stats_pass(lbm, wl, precision, steps):
-    """Newton iterations and rebuilt links per node over a short window."""
+def stats_pass(lbm, wl, precision, steps, settle=0):
+    """Newton iterations per solve and rebuilt links per node over a window
+    of `steps` steps after the same settling as the timed run."""
     sim = lbm.Sim.from_workload(wl, precision=precision, stats=True)
+    if settle:
+        sim.step(settle)
+    d0 = sim.diag()
     sim.step(steps)
     d = sim.diag()
     nodes = wl.nx * wl.ny * steps
     sim.close()
-    return dict(newton_iters_per_solve=d["newton_iters"] / max(d["newton_calls"], 1),
-                solves_per_node=d["newton_calls"] / nodes,
-                rebuilt_links_per_node=d["mismatched_links"] / nodes)
+    calls = d["newton_calls"] - d0["newton_calls"]
+    iters = d["newton_iters"] - d0["newton_iters"]
+    links = d["mismatched_links"] - d0["mismatched_links"]
+    return dict(newton_iters_per_solve=iters / max(calls, 1), solves_per_node=calls / nodes,
+                rebuilt_links_per_node=links / nodes, window_steps=steps, after_steps=settle)
 
 
-def copy_bandwidth(torch, mib=1024, reps=5):
-    """Measured device-copy bandwidth (bytes read + written per second) of a
-    plain 1 GiB copy, the best of a few: the practical HBM ceiling beside
-    the vendor's 8 TB/s."""
+def copy_bandwidth(torch, lbm, mib=2048, reps=5):
+    """Practical HBM ceiling: the library's streaming copy kernel (16-byte
+    nontemporal loads and stores) over 2 GiB, far beyond the caches, timed
+    with HIP events on the stream it is launched on; bytes read + written per
+    second, the best of a few."""
     n = (mib << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    lbm.stream_copy(src, dst, stream)
     best = float("inf")
     for _ in range(reps):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        dst.copy_(src)
-        b.record()
+        a.record(stream)
+        lbm.stream_copy(src, dst, stream)
+        b.record(stream)
         b.synchronize()
         best = min(best, a.elapsed_time(b) * 1e-3)
+    ok = bool(torch.equal(src[:1024], dst[:1024])) and bool(torch.equal(src[-1024:], dst[-1024:]))
     del src, dst
     torch.cuda.empty_cache()
+    if not ok:
+        raise RuntimeError("stream copy produced wrong data")
     return 2 * (mib << 20) / best / 1e9
+
+
+def host_cpu():
+    """Model, sockets and physical cores of the host (from /proc/cpuinfo)."""
+    model, phys = "", set()
+    cur = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    if cur:
+                        phys.add((cur.get("physical id"), cur.get("core id")))
+                    cur = {}
+                    continue
+                k, v = (t.strip() for t in line.split(":", 1))
+                cur[k] = v
+                if k == "model name" and not model:
+                    model = v
+        if cur:
+            phys.add((cur.get("physical id"), cur.get("core id")))
+    except OSError:
+        pass
+    sockets = len({p for p, _ in phys if p is not None}) or None
+    cores = len(phys) if phys and None not in {c for _, c in phys} else None
+    return dict(model=model, sockets=sockets, physical_cores=cores,
+                logical_cpus=os.cpu_count(), affinity_cpus=len(os.sched_getaffinity(0)))
 
 
 def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
@@ -156,7 +212,7 @@ def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
     import oracle
     half = 320
     sample = wl_full.window(wl_full.nx // 2, wl_full.ny // 2, half)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     s = oracle.Sim.from_workload(sample)
     n = 0
     t0 = time.perf_counter()
@@ -165,16 +221,13 @@ def cpu_baseline(wl_full, seconds_target=15.0, max_steps=40):
         n += 2
     dt = time.perf_counter() - t0
     nodes = sample.nx * sample.ny
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
+    cpu = host_cpu()
     return dict(value=round(nodes * n / dt / 1e6, 4), unit="MLUPS", cores=threads,
-                kind="oracle", cpu=model, host_cpus=os.cpu_count(),
+                kind="oracle", cpu=cpu["model"], sockets=cpu["sockets"],
+                physical_cores=cpu["physical_cores"], logical_cpus=cpu["logical_cpus"],
+                threads=threads,
                 sample=f"{sample.nx}x{sample.ny} periodic crop of the same initial field, "
-                       f"{n} steps, FP64, {dt:.1f} s")
+                       f"{n} steps, FP64, {dt:.1f} s, OpenMP threads {threads}")
 
 
 SERVE_JOBS = 128
@@ -229,6 +282,9 @@ def main():
                     help="skip the job-server pass (p50/p99 time-to-solution)")
     ap.add_argument("--no-counters", action="store_true",
                     help="skip the extra run with Newton and rebuild counters")
+    ap.add_argument("--settle", type=int, default=200,
+                    help="untimed plain steps before the warm-up, which carry the draw into "
+                         "its developed state (shift interfaces grown from the quadrant lines)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB three times "
                          "(calibrates the HBM byte counters) and exit")
@@ -248,11 +304,11 @@ def main():
         src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            lbm.stream_copy(src, dst)
         torch.cuda.synchronize()
         print(json.dumps(dict(copy_bytes=n, launches=3)), flush=True)
         return
-    wl = W.four_quadrant(args.size, args.warmup + args.steps)
+    wl = W.four_quadrant(args.size, args.settle + args.warmup + args.steps)
     res = {}
     for form in args.forms.split(","):
         print(f"[bench] timing {form} {args.size}^2, warmup {args.warmup}, steps {args.steps}",
@@ -262,7 +318,7 @@ def main():
             from paper_2009_13426_amd import autotune
             sched = autotune.schedule_for(form, args.size, args.size)
         res[form] = time_form(lbm, torch, wl, form, args.steps, args.warmup, sched,
-                              args.graph_chunk)
+                              args.graph_chunk, settle=args.settle)
         print(f"[bench] {form}: {res[form]['mlups']:.1f} MLUPS, step kernel "
               f"{res[form]['kernel_ms']:.3f} ms, rebuild kernel {res[form]['rebuild_ms']:.3f} ms",
               file=sys.stderr, flush=True)
@@ -270,7 +326,7 @@ def main():
     if not args.no_variants:
         print("[bench] timing the four-constraint variant (fp32)", file=sys.stderr, flush=True)
         v = time_form(lbm, torch, wl, "fp32", args.steps, args.warmup, None, args.graph_chunk,
-                      constraints=4)
+                      settle=args.settle, constraints=4)
         variants["fp32_constraints4"] = dict(
             mlups=round(v["mlups"], 2), kernel_ms=round(v["kernel_ms"], 4),
             rebuild_ms=round(v["rebuild_ms"], 4), status=v["status"],
@@ -280,7 +336,7 @@ def main():
         print("[bench] timing the flexible-Prandtl collision (fp32, Pr = 0.71)",
               file=sys.stderr, flush=True)
         v = time_form(lbm, torch, wl, "fp32", args.steps, args.warmup, None, args.graph_chunk,
-                      prandtl=0.71)
+                      settle=args.settle, prandtl=0.71)
         variants["fp32_prandtl_0.71"] = dict(
             mlups=round(v["mlups"], 2), kernel_ms=round(v["kernel_ms"], 4),
             rebuild_ms=round(v["rebuild_ms"], 4), status=v["status"],
@@ -302,10 +358,10 @@ def main():
     counters = {f: {} for f in res}
     if not args.no_counters:
         print("[bench] counters pass", file=sys.stderr, flush=True)
-        counters = {f: stats_pass(lbm, wl, f, 5) for f in res}
+        counters = {f: stats_pass(lbm, wl, f, args.steps, args.settle) for f in res}
 
     nodes = wl.nx * wl.ny
-    copy_gbs = copy_bandwidth(torch)
+    copy_gbs = copy_bandwidth(torch, lbm)
     prof = profile_figures()
     fresh = prof.get("source_sha256") == kernel_sources_digest() and \
         prof.get("size") == str(args.size)
@@ -317,17 +373,20 @@ def main():
         traffic = round(float(prof[f"{head}.fetch_bytes_per_launch"]) +
                         float(prof[f"{head}.write_bytes_per_launch"]))
     ach = flops * nodes / t_step / 1e12
-    hbm = bytes_per_node(head) * nodes / t_step / 1e9
-    roofline = dict(bound="alu", achieved=round(ach, 2), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(ach / FP64_PEAK_TFLOPS, 4), traffic=traffic,
-                    kernel="step_kernel", fp64_flops_per_node=flops,
+    hbm = algorithmic_bytes(head) * nodes / t_step / 1e9
+    roofline = dict(bound="hbm", achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(hbm / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel="step_kernel", bytes_per_node=algorithmic_bytes(head),
                     counters_match_kernel=fresh,
-                    valu_issue_frac=round(valu * nodes / t_step / VALU_ISSUE_PEAK, 4),
-                    hbm=dict(achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                             frac=round(hbm / HBM_PEAK_GBS, 4),
-                             copy_gbs=round(copy_gbs, 1),
-                             frac_of_copy=round(hbm / copy_gbs, 4),
-                             bytes_per_node=bytes_per_node(head)))
+                    copy_gbs=round(copy_gbs, 1), frac_of_copy=round(hbm / copy_gbs, 4),
+                    with_side_arrays=dict(
+                        bytes_per_node=bytes_per_node(head),
+                        achieved=round(bytes_per_node(head) * nodes / t_step / 1e9, 1)),
+                    alu=dict(fp64_flops_per_node=flops, achieved=round(ach, 2),
+                             peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                             frac=round(ach / FP64_PEAK_TFLOPS, 4),
+                             valu_insts_per_node=valu,
+                             valu_issue_frac=round(valu * nodes / t_step / VALU_ISSUE_PEAK, 4)))
     serving = None
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
@@ -347,12 +406,17 @@ def main():
         config=dict(workload=f"four-quadrant Riemann {args.size}x{args.size}, D2Q21 adaptive "
                              f"shifts, Knudsen sensor, nu={wl.nu:g}, seeded draw",
                     nodes=nodes, precision=head, schedule=res[head]["schedule"],
-                    graph_chunk=args.graph_chunk),
+                    graph_chunk=args.graph_chunk, settle_steps=args.settle,
+                    untimed_steps_before_timing=res[head]["untimed_steps"]),
         roofline=roofline, cpu_baseline=cpu, serving=serving, variants=variants or None,
         forms={f: dict(mlups=round(r["mlups"], 2), kernel_ms=round(r["kernel_ms"], 4),
                        rebuild_ms=round(r["rebuild_ms"], 4), schedule=r["schedule"],
-                       hbm_gbs=round(bytes_per_node(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9, 1),
-                       bytes_per_node=bytes_per_node(f), **counters[f])
+                       hbm_gbs=round(algorithmic_bytes(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9, 1),
+                       hbm_frac=round(algorithmic_bytes(f) * nodes / (r["kernel_ms"] * 1e-3) / 1e9
+                                      / HBM_PEAK_GBS, 4),
+                       frac_of_copy=round(algorithmic_bytes(f) * nodes / (r["kernel_ms"] * 1e-3)
+                                          / 1e9 / copy_gbs, 4),
+                       bytes_per_node=algorithmic_bytes(f), **counters[f])
                for f, r in res.items()},
     )
     print(json.dumps(line), flush=True)

@@ -269,6 +269,14 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
  * staging is shared by the process, and calls are serialised on it. */
 lbm_status lbm_step_batched_noalloc(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n);
 
+/* Copies `bytes` bytes from device buffer src to device buffer dst (16-byte
+ * aligned, not overlapping) on hip_stream with the library's streaming copy
+ * kernel (16-byte nontemporal loads and stores, several in flight per lane):
+ * the practical HBM bandwidth that the step kernels' traffic is measured
+ * against, beside the device's nominal peak.  Asynchronous; LBM_ERR_ARG for
+ * null or misaligned pointers. */
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
 /* Frees the host context; the workspace stays the caller's. */
 void lbm_destroy(lbm_ctx* ctx);
 

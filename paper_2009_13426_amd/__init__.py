@@ -243,3 +243,16 @@ def step_batched(sims: Sequence[Sim], nsteps: Sequence[int]):
     arr = (C.c_void_p * n)(*[s.handle.value for s in sims])
     steps = (C.c_int32 * n)(*[int(k) for k in nsteps])
     _check(lib.lbm_step_batched(arr, steps, n), "lbm_step_batched")
+
+
+def stream_copy(src, dst, stream=None):
+    """Copies the bytes of device tensor src into dst (same byte size) with
+    the library's streaming copy kernel, on `stream` (default: torch's
+    current stream); asynchronous."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy: src and dst differ in size")
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(lib.lbm_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                               nbytes, C.c_void_p(s.cuda_stream)), "lbm_stream_copy")

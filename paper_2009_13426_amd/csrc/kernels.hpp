@@ -25,9 +25,13 @@
 #ifndef LBM_HIST_BINS
 #define LBM_HIST_BINS 32
 #endif
-// Waves per SIMD the step kernel is compiled for (caps its registers).
+// Waves per SIMD the step kernel is compiled for (caps its registers): FP64
+// storage and FP32 storage.
 #ifndef LBM_STEP_WAVES_PER_EU
 #define LBM_STEP_WAVES_PER_EU 2
+#endif
+#ifndef LBM_STEP_WAVES_PER_EU_F32
+#define LBM_STEP_WAVES_PER_EU_F32 2
 #endif
 
 namespace lbm {
@@ -369,14 +373,21 @@ __device__ __forceinline__ void carried_uT(const S* mac, const int* tags, long l
 // The numerical equilibrium of the context's constraint set: the 8-moment
 // set (eq. feqNum_8Mom, default) or mass, momentum and energy only (M = 4,
 // eq. feqNum_4Mom).
-template <int M>
+// POLISH: the final correction after the stopping criterion (reading of
+// the FP64 form; see solve_fast).
+template <int M, bool POLISH = true>
 __device__ __forceinline__ NewtonOut solve_of(const GuessTable& tb, double ux, double uy,
                                               double T, const Phys& P, Weights& w) {
   if constexpr (M == 4)
     return solve_equilibrium4(tb, ux, uy, T, P.tol, P.max_iter, w);
   else
-    return solve_equilibrium(tb, ux, uy, T, P.tol, P.max_iter, w);
+    return solve_equilibrium<POLISH>(tb, ux, uy, T, P.tol, P.max_iter, w);
 }
+
+// The FP64 form polishes every solve to round-off (its parity with the
+// oracle is 1e-12); the FP32-storage form stops at the criterion.
+template <typename S>
+constexpr bool kPolish = std::is_same<S, double>::value;
 
 // Post-collision population of velocity plane k in the receiver's lattice
 // (Lx, Ly), rebuilt at source node s by Grad's ansatz from the moments of
@@ -416,7 +427,7 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
     dT[1] = 0.5 * (Sp - Sm);
   }
   Weights w;
-  const NewtonOut no = solve_of<M>(a.table, ux - Lx, uy - Ly, T, P, w);
+  const NewtonOut no = solve_of<M, kPolish<S>>(a.table, ux - Lx, uy - Ly, T, P, w);
   iters = no.iters;
   if (!no.ok) return kCodeNewton;
   double wk = 0.0, cxk = 0.0, cyk = 0.0;
@@ -552,6 +563,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   // parked in LDS; moments in the frame of the node's lattice (eq. polyTemp)
   double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
   PullMap pm;  // sources of this pull; the next pull reuses them unless the lattice changes
+  int st[kQ];  // tags of the next pull's sources, loaded with this pull's populations
   if (active) {
     S fv[kQ], gv[kQ];
     if constexpr (STREAM) {
@@ -562,6 +574,12 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
         fv[k] = plane_at(fin + k * N, i);
         gv[k] = plane_at(gin + k * N, i);
       });
+      if (P.shift_mode != 1) {
+        static_for<0, kQ>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          st[k] = plane_at(a.tin, pm.template source<k>());
+        });
+      }
       // rebuilt links (rare: a wave-uniform test skips this for most waves)
       if (__ballot(mism != 0u)) {
         static_for<0, kQ>([&](auto kc) {
@@ -630,13 +648,15 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     // links of the next pull whose source collides in another lattice this
     // step (the source's lattice of this step is the Un half of its tag)
     if (P.shift_mode != 1) {
-      if (!STREAM || nux != unx || nuy != uny) pm.build(x, y, nux, nuy, a.grid);
+      if (!STREAM || nux != unx || nuy != uny) {
+        // the lattice changes (or nothing was pulled): other sources
+        pm.build(x, y, nux, nuy, a.grid);
+        static_for<0, kQ>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          st[k] = plane_at(a.tin, pm.template source<k>());
+        });
+      }
       const int nun16 = (nux & 0xFF) | ((nuy & 0xFF) << 8);
-      int st[kQ];
-      static_for<0, kQ>([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        st[k] = plane_at(a.tin, pm.template source<k>());
-      });
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         if (tag_un16(st[k]) != nun16) next_mask |= 1u << k;
@@ -644,7 +664,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     }
     if (physical) {
       // a5: numerical equilibrium
-      const NewtonOut no = solve_of<M>(a.table, upx, upy, T, P, w);
+      const NewtonOut no = solve_of<M, kPolish<S>>(a.table, upx, upy, T, P, w);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -770,9 +790,13 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
 // TILED: each workgroup runs a.tiles consecutive tiles in a loop (the loop
 // keeps kernel arguments live across the body, which costs spills); else
 // one tile per workgroup.
+template <typename S>
+constexpr int kStepWaves =
+    std::is_same<S, float>::value ? LBM_STEP_WAVES_PER_EU_F32 : LBM_STEP_WAVES_PER_EU;
+
 template <typename S, bool STREAM, int BLOCK, bool TILED, int M = kM, bool NBH = false,
           bool PR = false>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(kStepWaves<S>)))
 void step_kernel(StepArgs a) {
   const int g = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : static_cast<int>(blockIdx.x);
   if constexpr (TILED) {
@@ -1172,6 +1196,40 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a) {
     fo[k * N + n] = static_cast<S>(feq * (1.0 + phif));
     go[k * N + n] = static_cast<S>(gfac * feq * (1.0 + phig));
   });
+}
+
+// ------------------------------------------------------------ copy
+// Streaming device copy: the practical HBM ceiling the step kernels are
+// measured against.  Each lane moves kCopyUnroll 16-byte words per pass
+// (all loads in flight before the first store), nontemporal so that the
+// stream does not displace anything else from the caches; grid-stride.
+constexpr int kCopyUnroll = 4;
+typedef float CopyWord __attribute__((ext_vector_type(4)));  // 16 bytes
+
+__global__ __launch_bounds__(kBlock) void stream_copy_kernel(const CopyWord* __restrict__ src,
+                                                             CopyWord* __restrict__ dst,
+                                                             long long words) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock * kCopyUnroll;
+  for (long long base = static_cast<long long>(blockIdx.x) * kBlock * kCopyUnroll + threadIdx.x;
+       base < words; base += stride) {
+    CopyWord v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const long long i = base + static_cast<long long>(u) * kBlock;
+      if (i < words) v[u] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const long long i = base + static_cast<long long>(u) * kBlock;
+      if (i < words) __builtin_nontemporal_store(v[u], dst + i);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void copy_tail_kernel(const unsigned char* src,
+                                                           unsigned char* dst, long long n) {
+  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------ exports

@@ -1095,6 +1095,35 @@ lbm_status lbm_step_batched_noalloc(lbm_ctx* const* ctxs, const int32_t* nsteps,
                              g_noalloc_host_jobs, g_noalloc_host_keys);
 }
 
+lbm_status lbm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (bytes == 0) return LBM_OK;
+  if (!src || !dst) return LBM_ERR_ARG;
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return LBM_ERR_ARG;
+  hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+  const long long words = static_cast<long long>(bytes / 16);
+  if (words > 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return LBM_ERR_HIP;
+    // eight workgroups per compute unit, enough passes to amortise the tail
+    const long long per_pass = static_cast<long long>(kBlock) * kCopyUnroll;
+    const long long need = (words + per_pass - 1) / per_pass;
+    const unsigned blocks = static_cast<unsigned>(std::min<long long>(need, 8ll * cus));
+    hipLaunchKernelGGL(stream_copy_kernel, dim3(blocks), dim3(kBlock), 0, stream,
+                       static_cast<const CopyWord*>(src), static_cast<CopyWord*>(dst), words);
+  }
+  const long long tail = static_cast<long long>(bytes % 16);
+  if (tail) {
+    const long long off = words * 16;
+    hipLaunchKernelGGL(copy_tail_kernel, dim3(1), dim3(kBlock), 0, stream,
+                       static_cast<const unsigned char*>(src) + off,
+                       static_cast<unsigned char*>(dst) + off, tail);
+  }
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
 void lbm_destroy(lbm_ctx* c) { delete c; }
 
 const char* lbm_status_str(lbm_status s) {
