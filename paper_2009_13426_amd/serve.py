@@ -61,11 +61,18 @@ class Report:
     quanta: int
 
     def summary(self) -> Dict:
+        """p50/p99/mean time-to-solution over the jobs that completed, and
+        p50_all/p99_all over every job, a failed one counted at the time its
+        failure was reported (its time to a final answer)."""
         ok = [r for r in self.results if r.status == 0]
         tts = np.array([r.time_to_solution for r in ok]) if ok else np.zeros(1)
+        tall = np.array([r.time_to_solution for r in self.results]) if self.results \
+            else np.zeros(1)
         work = sum(r.nodes * r.steps for r in ok)
         return dict(jobs=len(self.results), failed=len(self.results) - len(ok),
                     p50_s=float(np.percentile(tts, 50)), p99_s=float(np.percentile(tts, 99)),
+                    p50_all_s=float(np.percentile(tall, 50)),
+                    p99_all_s=float(np.percentile(tall, 99)),
                     mean_s=float(tts.mean()),
                     mean_wait_s=float(np.mean([r.admitted - r.arrival for r in ok])) if ok else 0.0,
                     makespan_s=self.makespan,
@@ -82,7 +89,9 @@ def serve(requests: Sequence[Request], engine, memory_budget: int, quantum: int 
     request that does not fit waits, and so do the ones behind it: no
     overtaking); then advance every admitted job by min(quantum, steps left)
     steps in one batched call.  A request larger than the whole budget is
-    refused (status -2 in its result)."""
+    refused (status -2 in its result).  The batch never holds more jobs than
+    the engine takes in one call (engine.max_batch)."""
+    max_batch = min(max_batch, getattr(engine, "max_batch", max_batch))
     pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.job_id)))
     active: List[Dict] = []
     results: List[Result] = []
@@ -155,6 +164,32 @@ def serve_one_at_a_time(requests: Sequence[Request], engine,
 
 
 # ----------------------------------------------------------------- engines
+# Statuses of a job that stopped on its own numbers (a failed equilibrium
+# solve, a non-physical state): the job fails, the batch goes on.
+NUMERICAL_FAILURES = (-5, -6)  # lbm_status LBM_ERR_NEWTON, LBM_ERR_NONPHYSICAL
+
+
+class BatchError(RuntimeError):
+    """A batched call failed for a reason other than a job's numerics (bad
+    argument, HIP error, call out of order): no job can be trusted to have
+    advanced, so the server stops instead of retiring them as done."""
+
+    def __init__(self, status: int):
+        super().__init__(f"batched step failed with status {status}")
+        self.status = status
+
+
+def batch_statuses(status: int, n: int, job_status: Callable[[int], int]) -> List[int]:
+    """Per-job statuses after a batched call that returned `status`: all 0
+    on success; on a numerical failure, each job's own status (job_status(k)
+    reads job k's device error word); any other status raises BatchError."""
+    if status == 0:
+        return [0] * n
+    if status in NUMERICAL_FAILURES:
+        return [int(job_status(k)) for k in range(n)]
+    raise BatchError(status)
+
+
 class GpuEngine:
     """Jobs as `Sim` contexts on one device and one stream; batched steps
     through `lbm_step_batched`.  Every context copies the initial-guess table
@@ -207,15 +242,15 @@ class GpuEngine:
             sim.schedule = self.batch_schedule
         return sim
 
+    max_batch = 1024  # contexts per lbm_step_batched call
+
     def run(self, sims, steps) -> List[int]:
         import ctypes as C
         n = len(sims)
         arr = (C.c_void_p * n)(*[s.handle.value for s in sims])
         ks = (C.c_int32 * n)(*[int(k) for k in steps])
         st = self.lib.lbm_step_batched(arr, ks, n)
-        if st == 0:
-            return [0] * n
-        return [int(self.lib.lbm_sync(s.handle)) for s in sims]
+        return batch_statuses(int(st), n, lambda k: self.lib.lbm_sync(sims[k].handle))
 
     def run_alone(self, sim, steps: int) -> int:
         if self.auto:
@@ -289,3 +324,123 @@ def requests_from_specs(specs, rate: float, prebuild: bool = False) -> List[Requ
         out.append(Request(sp.job_id, t if math.isfinite(rate) else 0.0, sp.side, sp.side,
                            sp.steps, make))
     return out
+
+
+class Prefetcher:
+    """Draws the jobs' initial fields ahead of their arrivals on a host
+    thread, in arrival order, at most `ahead` jobs in advance (a client that
+    has its fields ready when it submits); `make(k)` blocks until job k's
+    fields are drawn."""
+
+    def __init__(self, specs, ahead: int = 256):
+        import threading
+        self.specs = list(specs)
+        self.ready: Dict[int, object] = {}
+        self.cv = threading.Condition()
+        self.next = 0
+        self.ahead = ahead
+        self.taken = 0
+        self.thread = threading.Thread(target=self._run, daemon=True)
+        self.thread.start()
+
+    def _run(self):
+        for k, sp in enumerate(self.specs):
+            with self.cv:
+                while k - self.taken >= self.ahead:
+                    self.cv.wait()
+            wl = sp.build()
+            with self.cv:
+                self.ready[k] = wl
+                self.cv.notify_all()
+
+    def make(self, k: int):
+        with self.cv:
+            while k not in self.ready:
+                self.cv.wait()
+            wl = self.ready.pop(k)
+            self.taken = max(self.taken, k + 1)
+            self.cv.notify_all()
+        return wl
+
+
+def requests_prefetched(specs, rate: float, ahead: int = 256) -> List[Request]:
+    """As requests_from_specs, with the fields drawn ahead by a Prefetcher."""
+    pf = Prefetcher(specs, ahead)
+    out, t = [], 0.0
+    for k, sp in enumerate(specs):
+        if math.isfinite(rate):
+            t += sp.interarrival / rate
+        out.append(Request(sp.job_id, t if math.isfinite(rate) else 0.0, sp.side, sp.side,
+                           sp.steps, (lambda k=k: pf.make(k))))
+    return out
+
+
+def main(argv=None):
+    """The seeded serving mix through the batched server: capacity with the
+    first --capacity-jobs jobs queued at t = 0, then --jobs Poisson arrivals
+    at --load times that capacity.  Prints progress and one JSON summary.
+
+      python -m paper_2009_13426_amd.serve --jobs 10000 --capacity-jobs 2000
+    """
+    import argparse
+    import json
+    import os
+    import sys
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=10000)
+    ap.add_argument("--capacity-jobs", type=int, default=2000)
+    ap.add_argument("--load", type=float, default=0.8)
+    ap.add_argument("--quantum", type=int, default=50)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--budget-frac", type=float, default=0.6)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import torch
+    import workloads as W
+    from . import autotune
+    torch.cuda.set_device(0)
+    specs = W.serving_jobs(args.jobs)
+    eng = GpuEngine(precision=args.precision)
+    eng.batch_schedule = autotune.batched_schedule_for(args.precision, device=eng.device)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(args.budget_frac * free)
+    t0 = time.time()
+
+    def progress(tag, total):
+        done = [0]
+
+        def on_finish(req, handle):
+            done[0] += 1
+            if done[0] % 250 == 0 or done[0] == total:
+                print(f"[serve] {tag}: {done[0]}/{total} jobs done, {time.time() - t0:.0f} s",
+                      flush=True)
+        return on_finish
+
+    cap_specs = specs[:args.capacity_jobs]
+    cap = serve(requests_prefetched(cap_specs, math.inf), eng, budget, args.quantum,
+                on_finish=progress("capacity", len(cap_specs))).summary()
+    rate = args.load * cap["jobs_per_s"]
+    print(f"[serve] capacity {cap['jobs_per_s']:.2f} jobs/s on {len(cap_specs)} jobs; "
+          f"arrivals at {rate:.2f} jobs/s", flush=True)
+    rep = serve(requests_prefetched(specs, rate), eng, budget, args.quantum,
+                on_finish=progress("trace", len(specs)))
+    summ = rep.summary()
+    failed = [dict(job=r.job_id, status=r.status) for r in rep.results if r.status != 0]
+    out = dict(jobs=args.jobs, capacity_jobs=args.capacity_jobs,
+               capacity_jobs_per_s=cap["jobs_per_s"], capacity_mlups=cap["mlups"],
+               load=args.load, rate_jobs_per_s=rate, quantum=args.quantum,
+               precision=args.precision, memory_budget_bytes=budget,
+               batched_schedule=eng.batch_schedule, summary=summ, failed_jobs=failed,
+               wall_s=time.time() - t0)
+    line = json.dumps(out)
+    print(line, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()

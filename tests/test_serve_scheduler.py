@@ -122,3 +122,30 @@ def test_requests_from_specs_arrival_times():
     rq0 = S.requests_from_specs(specs, rate=math.inf)
     assert all(r.arrival == 0.0 for r in rq0)
     assert all(r.nx == sp.side and r.steps == sp.steps for r, sp in zip(rq, specs))
+
+
+def test_batch_statuses_only_numerical_failures_fall_back():
+    """A job's own numerical failure (LBM_ERR_NEWTON -5, NONPHYSICAL -6)
+    gives each job its status; any other error of the batched call (bad
+    argument -1, HIP -3, out of order -4) stops the server instead of
+    retiring every job as if it had advanced."""
+    own = {0: 0, 1: -5, 2: 0}
+    assert S.batch_statuses(0, 3, own.__getitem__) == [0, 0, 0]
+    assert S.batch_statuses(-5, 3, own.__getitem__) == [0, -5, 0]
+    assert S.batch_statuses(-6, 3, own.__getitem__) == [0, -5, 0]
+    for st in (-1, -2, -3, -4):
+        with pytest.raises(S.BatchError):
+            S.batch_statuses(st, 3, own.__getitem__)
+
+
+class _LimitEngine(S.FakeEngine):
+    max_batch = 4
+
+
+def test_batch_never_exceeds_the_engines_limit():
+    rq = reqs([(0.0, 64, 100) for _ in range(10)])
+    eng = _LimitEngine()
+    rep = S.serve(rq, eng, memory_budget=10**12, quantum=50, max_batch=1024)
+    sizes = [len(ev[1]) for ev in eng.log if ev[0] == "run"]
+    assert max(sizes) == 4
+    assert len(rep.results) == 10 and all(r.status == 0 for r in rep.results)

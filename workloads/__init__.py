@@ -214,13 +214,34 @@ def riemann_table1(L: int = 200, nu: float = 1e-3, steps: int = 100) -> Workload
 QUADRANT_NU = 1e-3
 
 
+def initial_lattice(u: float) -> int:
+    """Lattice shift of a velocity component at t = 0 (eq. criterion)."""
+    return int(math.ceil(u - 0.5))
+
+
+def links_within(states, max_speed: float) -> bool:
+    """True if every quadrant's state, seen in every other quadrant's initial
+    lattice, moves at most max_speed relative to that lattice: the states the
+    first steps rebuild links at (a rebuilt link takes the source's state in
+    the receiver's lattice)."""
+    for a in states:
+        for b in states:
+            Ux, Uy = initial_lattice(b[1]), initial_lattice(b[2])
+            if math.hypot(a[1] - Ux, a[2] - Uy) > max_speed:
+                return False
+    return True
+
+
 def draw_quadrant_states(rng: np.random.Generator, mach_range=(0.0, 3.0),
-                         mach: float | None = None, T_ref: float = T0):
+                         mach: float | None = None, T_ref: float = T0,
+                         max_link_speed: float | None = None):
     """Seeded four-quadrant draw: a common velocity (Mach in mach_range w.r.t.
     T_ref, random direction), then per quadrant rho ~ U[0.5, 1.5] and
     p ~ U[0.03, 1.5] redrawn until T = p / rho lies in [0.5, 1.4], plus a
     velocity perturbation of magnitude U[0, 0.75] in a random direction.
-    Draws with T_max / T_min > 2 are rejected as a whole."""
+    Draws with T_max / T_min > 2 are rejected as a whole, and so are draws
+    with a quadrant moving faster than max_link_speed relative to another
+    quadrant's lattice (when given)."""
     c0 = math.sqrt(GAMMA * T_ref)
     while True:
         M = rng.uniform(*mach_range) if mach is None else mach
@@ -237,15 +258,17 @@ def draw_quadrant_states(rng: np.random.Generator, mach_range=(0.0, 3.0),
             ph = rng.uniform(0.0, 2 * math.pi)
             states.append((rho, U[0] + a * math.cos(ph), U[1] + a * math.sin(ph), p))
         Ts = [s[3] / s[0] for s in states]
-        if max(Ts) / min(Ts) <= 2.0:
+        if max(Ts) / min(Ts) <= 2.0 and (max_link_speed is None or
+                                         links_within(states, max_link_speed)):
             return states, M
 
 
 def four_quadrant(L: int = 4096, steps: int = 1000, seed_index: int = 3,
                   nu: float | None = None, sub: int = 0,
-                  mach: float | None = None) -> Workload:
+                  mach: float | None = None,
+                  max_link_speed: float | None = None) -> Workload:
     rng = rng_for(seed_index, sub)
-    states, M = draw_quadrant_states(rng, mach=mach)
+    states, M = draw_quadrant_states(rng, mach=mach, max_link_speed=max_link_speed)
     rho, ux, uy, T = quadrant_fields(L, states)
     return Workload(f"quadrant_{L}x{L}_s{seed_index}.{sub}", L, L, rho, ux, uy, T,
                     QUADRANT_NU if nu is None else nu, steps, sensor=1,
@@ -257,6 +280,26 @@ def config3(L: int = 4096, steps: int = 1000) -> Workload:
 
 
 # ------------------------------------------------------------ serving mix
+# Viscosity of each job type of the serving mix: the smallest value of the
+# ladder {1e-3, 2e-3, 5e-3, 1e-2, 2e-2} (the four-quadrant draws' rule) at
+# which the mix's draws of that type run to their last step without an
+# equilibrium failure; None keeps the type's own default (the vortex's
+# 1e-4 T_inf).
+NU_LADDER = (1e-3, 2e-3, 5e-3, 1e-2, 2e-2)
+SERVING_NU = {"vortex": None, "quadrant": 1e-3}
+# Quadrant draws of the mix whose states, seen in another quadrant's lattice,
+# move faster than this are redrawn: the first step rebuilds links at those
+# states, and beyond about 1.5 (e.g. |u'| = 1.75 across a diagonal lattice
+# jump) the 8-moment D2Q21 equilibrium has no solution, at any viscosity.
+SERVING_MAX_LINK_SPEED = 1.5
+# Hysteresis half-width of the lattice choice per job type (overlapping
+# velocity ranges chosen by history, Sec. III.A.2; 0.5 is the plain
+# criterion).  Strong shocks of the quadrant draws otherwise put nodes whose
+# lattices differ by two next to each other, and the links rebuilt between
+# them leave the equilibrium's envelope at any viscosity of the ladder.
+SERVING_HALFWIDTH = {"vortex": 0.5, "quadrant": 0.9}
+
+
 @dataclasses.dataclass
 class JobSpec:
     job_id: int
@@ -265,13 +308,20 @@ class JobSpec:
     mach: float
     steps: int
     interarrival: float  # unit-rate exponential draw; divide by the rate
+    nu: float | None = None   # None: SERVING_NU of the job's type
 
     def build(self) -> Workload:
+        nu = self.nu if self.nu is not None else SERVING_NU[self.kind]
         if self.kind == "vortex":
-            return isentropic_vortex(self.side, mach=self.mach, steps=self.steps,
-                                     seed_index=4, name=f"job{self.job_id}_vortex")
-        return four_quadrant(self.side, self.steps, seed_index=4,
-                             sub=self.job_id + 1, mach=self.mach)
+            wl = isentropic_vortex(self.side, mach=self.mach, steps=self.steps,
+                                   seed_index=4, name=f"job{self.job_id}_vortex", nu=nu)
+            wl.halfwidth = SERVING_HALFWIDTH["vortex"]
+            return wl
+        wl = four_quadrant(self.side, self.steps, seed_index=4,
+                           sub=self.job_id + 1, mach=self.mach, nu=nu,
+                           max_link_speed=SERVING_MAX_LINK_SPEED)
+        wl.halfwidth = SERVING_HALFWIDTH["quadrant"]
+        return wl
 
     @property
     def work(self) -> int:
