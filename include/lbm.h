@@ -256,6 +256,18 @@ lbm_status lbm_get_diag(lbm_ctx* ctx, lbm_diag* out);
  * which). */
 lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n);
 
+/* As lbm_step_batched (same arguments, results bit for bit, errors), with
+ * the quantum's launches (per step the rebuild and the step launch) recorded
+ * as a HIP graph of kernel nodes and replayed: form (2)'s step loop in a
+ * graph.  The graph is kept by ctxs[0] and rebuilt only when the launch
+ * shape changes (number of contexts, the largest nsteps, the contexts'
+ * grid sizes or ctxs[0]'s schedule); the kernels read the job table at a
+ * fixed address in ctxs[0]'s workspace, which is refreshed before every
+ * replay.  graph_built (host pointer, nullable): 1 if this call recorded
+ * the graph, 0 if it replayed the kept one. */
+lbm_status lbm_step_batched_graph(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n,
+                                  int32_t* graph_built);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): lbm_step_batched with
  * the same arguments, results and errors, except that the job table and the

@@ -237,12 +237,20 @@ class Sim:
             pass
 
 
-def step_batched(sims: Sequence[Sim], nsteps: Sequence[int]):
-    """Advances several simulations sharing one stream, nsteps[k] steps each."""
+def step_batched(sims: Sequence[Sim], nsteps: Sequence[int], graph: bool = False):
+    """Advances several simulations sharing one stream, nsteps[k] steps each.
+    graph: replay the quantum as a HIP graph kept by sims[0]
+    (lbm_step_batched_graph); returns 1 if the graph was recorded by this
+    call, 0 if it was replayed (None without graph)."""
     n = len(sims)
     arr = (C.c_void_p * n)(*[s.handle.value for s in sims])
     steps = (C.c_int32 * n)(*[int(k) for k in nsteps])
-    _check(lib.lbm_step_batched(arr, steps, n), "lbm_step_batched")
+    if not graph:
+        _check(lib.lbm_step_batched(arr, steps, n), "lbm_step_batched")
+        return None
+    built = C.c_int32(0)
+    _check(lib.lbm_step_batched_graph(arr, steps, n, C.byref(built)), "lbm_step_batched_graph")
+    return built.value
 
 
 def stream_copy(src, dst, stream=None):

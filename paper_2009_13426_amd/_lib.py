@@ -63,6 +63,8 @@ SIGNATURES = {
     "lbm_step_batched": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_int32), C.c_int32]),
     "lbm_step_batched_noalloc": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
                                            C.c_int32]),
+    "lbm_step_batched_graph": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                         C.c_int32, C.POINTER(C.c_int32)]),
     "lbm_stream_copy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "lbm_destroy": (None, [C.c_void_p]),
     "lbm_status_str": (C.c_char_p, [C.c_int]),

@@ -1,10 +1,12 @@
 """Autotuner of the step loop's launch schedule.
 
 The per-node work of a step is fixed; what can be chosen is how nodes map to
-workgroups (`lbm_schedule`): lanes per workgroup of the step kernel, tiles a
-workgroup runs one after the other, the XCD-aware tile order, and the
-workgroup count of the link-rebuild launch.  Every schedule gives bitwise
-the same results, so the choice is by time alone.
+workgroups (`lbm_schedule`): lanes per workgroup of the step kernel, nodes
+per lane (a workgroup runs that many consecutive tiles one after the other,
+each lane taking one node of every tile in turn: `tiles_per_block`), the
+XCD-aware tile order, and the workgroup count of the link-rebuild launch.
+Every schedule gives bitwise the same results, so the choice is by time
+alone.
 
 The tuner times each candidate on a throw-away simulation (its steps are
 never part of a user's run), restored before every timing to one state of
@@ -26,7 +28,7 @@ from typing import Callable, Dict, Iterable, List, Optional, Tuple
 
 CACHE_ENV = "LBM_SCHEDULE_CACHE"
 STEP_BLOCKS = {"fp64": (64, 128), "fp32": (64, 128, 256)}
-TILES = (1, 2, 4)
+TILES = (1, 2, 4, 8)   # nodes per lane (tiles per workgroup)
 REMAPS = (1, 0)
 REBUILD_BLOCKS = (0, 256, 1024, 8192)
 MARGIN = 0.02   # relative gain a candidate needs over the best so far
@@ -111,7 +113,8 @@ def choose(sim, precision, steps: int = 8, repeats: int = 2,
     best, best_t = None, math.inf
     for cand in (step_cands if step_cands is not None else step_candidates(precision)):
         r, s = timer(sim, dict(cand, rebuild_blocks=0), steps, repeats, reset)
-        trials.append(dict(cand, rebuild_blocks=0, step_ms=s, rebuild_ms=r))
+        trials.append(dict(cand, rebuild_blocks=0, nodes_per_lane=cand.get("tiles_per_block", 1),
+                           step_ms=s, rebuild_ms=r))
         if s < best_t * (1.0 - margin):
             best, best_t = dict(cand), s
     best_rb, best_rt = 0, math.inf

@@ -624,14 +624,10 @@ __device__ __forceinline__ void constraint_moments(const Weights& w, double (&c)
 }
 
 // Table start, then Newton steps applied to the weights multiplicatively (no
-// multipliers are carried).  Stops on max |G| <= tol.  POLISH: then one
-// first-order final correction, solved with the factors of the last step,
-// which are kept in registers (the residual is at the tolerance, so factors
-// of a Hessian that moved by the size of that step take it to round-off);
-// without it the weights meet the stopping criterion only, which is what
-// the FP32-storage form keeps (its populations are rounded to FP32, 6e-8,
-// four orders of magnitude above the criterion).
-template <bool POLISH = true>
+// multipliers are carried).  Stops on max |G| <= tol with a first-order
+// final correction, solved with the factors of the last step, which are
+// kept in registers: the residual is at the tolerance, so factors of a
+// Hessian that moved by the size of that step take it to round-off.
 __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux, double uy,
                                                 double T, double tol, int max_iter, Weights& w) {
   NewtonOut out{0, false};
@@ -680,12 +676,10 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
     for (int a = 0; a < kM; ++a) r = fmax(r, fabs(G[a]));
     out.iters = it + 1;
     if (!(r < 1e300)) return out;
-    if (r <= tol && (it > 0 || !POLISH)) {
-      if constexpr (POLISH) {
-        // final correction with the last step's factors
-        ldl_solve_inplace(A, G);
-        linear_update(G, w);
-      }
+    if (r <= tol && it > 0) {
+      // final correction with the last step's factors
+      ldl_solve_inplace(A, G);
+      linear_update(G, w);
       out.ok = true;
       return out;
     }
@@ -718,11 +712,10 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
 
 // solve_fast, and where it fails (a state far from the table or a start
 // from which plain Newton steps do not converge) the globalised solve_robust.
-template <bool POLISH = true>
 __device__ __forceinline__ NewtonOut solve_equilibrium(const GuessTable& tb, double ux, double uy,
                                                        double T, double tol, int max_iter,
                                                        Weights& w) {
-  NewtonOut out = solve_fast<POLISH>(tb, ux, uy, T, tol, max_iter, w);
+  NewtonOut out = solve_fast(tb, ux, uy, T, tol, max_iter, w);
   if (!out.ok) {
     double l[kM];
     const NewtonOut r = solve_robust(ux, uy, T, tol, max_iter, w, l);

@@ -373,21 +373,14 @@ __device__ __forceinline__ void carried_uT(const S* mac, const int* tags, long l
 // The numerical equilibrium of the context's constraint set: the 8-moment
 // set (eq. feqNum_8Mom, default) or mass, momentum and energy only (M = 4,
 // eq. feqNum_4Mom).
-// POLISH: the final correction after the stopping criterion (reading of
-// the FP64 form; see solve_fast).
-template <int M, bool POLISH = true>
+template <int M>
 __device__ __forceinline__ NewtonOut solve_of(const GuessTable& tb, double ux, double uy,
                                               double T, const Phys& P, Weights& w) {
   if constexpr (M == 4)
     return solve_equilibrium4(tb, ux, uy, T, P.tol, P.max_iter, w);
   else
-    return solve_equilibrium<POLISH>(tb, ux, uy, T, P.tol, P.max_iter, w);
+    return solve_equilibrium(tb, ux, uy, T, P.tol, P.max_iter, w);
 }
-
-// The FP64 form polishes every solve to round-off (its parity with the
-// oracle is 1e-12); the FP32-storage form stops at the criterion.
-template <typename S>
-constexpr bool kPolish = std::is_same<S, double>::value;
 
 // Post-collision population of velocity plane k in the receiver's lattice
 // (Lx, Ly), rebuilt at source node s by Grad's ansatz from the moments of
@@ -427,7 +420,7 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
     dT[1] = 0.5 * (Sp - Sm);
   }
   Weights w;
-  const NewtonOut no = solve_of<M, kPolish<S>>(a.table, ux - Lx, uy - Ly, T, P, w);
+  const NewtonOut no = solve_of<M>(a.table, ux - Lx, uy - Ly, T, P, w);
   iters = no.iters;
   if (!no.ok) return kCodeNewton;
   double wk = 0.0, cxk = 0.0, cyk = 0.0;
@@ -614,6 +607,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
 
   unsigned next_mask = 0u;
   if (active) {
+    // exact divisions, as the oracle takes them, in both forms: at tau close
+    // to 1/2 the flows carry small differences a long way (a reciprocal of
+    // rho here together with solves stopped without their final correction
+    // moved the FP32 form's 256^2 vortex by 1e-3 to 4e-3 after 1250 steps,
+    // against 3e-5)
     const double upx = jx / rho, upy = jy / rho;
     const double T = (e - rho * (upx * upx + upy * upy)) / (2.0 * rho * P.Cv);
     unsigned code = 0;
@@ -664,7 +662,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     }
     if (physical) {
       // a5: numerical equilibrium
-      const NewtonOut no = solve_of<M, kPolish<S>>(a.table, upx, upy, T, P, w);
+      const NewtonOut no = solve_of<M>(a.table, upx, upy, T, P, w);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -688,6 +686,19 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
       for (int p = 0; p < kPairs; ++p) {
         fe.wp[p] = rho * w.wp[p];
         fe.wm[p] = rho * w.wm[p];
+      }
+      // FP32-storage form (BGK): f_eq rounded to FP32 once for the collision,
+      // which runs in FP32 arithmetic (as it did before this array).  The sensor stays FP64 in both forms:
+      // at tau close to 1/2 the viscosity it adds, (alpha tau - 1/2) T, is
+      // sensitive to alpha (FP32 sums of eps moved the 256^2 vortex by 6e-4
+      // after 1250 steps, against 3e-5 in FP64)
+      constexpr bool k32 = std::is_same<S, float>::value && !PR;
+      float fe32[k32 ? kQ : 1];
+      if constexpr (k32) {
+        static_for<0, kQ>([&](auto kc) {
+          constexpr int k = decltype(kc)::value;
+          fe32[k] = static_cast<float>(weight_of<k>(fe));
+        });
       }
       double tau = 0.5 + P.nu / T;
       if (P.sensor) {
@@ -737,18 +748,21 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
       } else
       static_for<0, kQ>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const double feq = weight_of<k>(fe);
-        const double geq = gfac * feq;
         const S fk = sh_pop[k][tid], gk = sh_pop[kQ + k][tid];
         if constexpr (std::is_same<S, double>::value) {
+          const double feq = weight_of<k>(fe);
+          const double geq = gfac * feq;
           plane_at(fout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, feq - fk, fk);
           plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fma(om, geq - gk, gk);
         } else {
+          // g_eq from the FP64 product, rounded once: a product of rounded
+          // FP32 factors is biased the same way at every node of a state, and
+          // that bias accumulates over the steps (it moved the 256^2 vortex
+          // by 1e-3 after 1250 steps)
           const float omf = static_cast<float>(om);
-          plane_at(fout + k * N, static_cast<unsigned>(n)) =
-              __builtin_fmaf(omf, static_cast<float>(feq) - fk, fk);
-          plane_at(gout + k * N, static_cast<unsigned>(n)) =
-              __builtin_fmaf(omf, static_cast<float>(geq) - gk, gk);
+          const float geq = static_cast<float>(gfac * weight_of<k>(fe));
+          plane_at(fout + k * N, static_cast<unsigned>(n)) = __builtin_fmaf(omf, fe32[k] - fk, fk);
+          plane_at(gout + k * N, static_cast<unsigned>(n)) = __builtin_fmaf(omf, geq - gk, gk);
         }
       });
     }

@@ -152,6 +152,31 @@ struct StepGraph {
   }
 };
 
+// The launches of a batched quantum recorded as a HIP graph (kernel nodes
+// only), kept by the batch's first context.  The kernels read the job
+// table at a fixed device address, so a replay needs only a fresh table;
+// the graph is rebuilt when the launch shape changes (job count, steps of
+// the quantum, grid sizes, schedule).
+struct BatchGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* jobs = nullptr;
+  int njobs = -1, most = -1, B = 0, remap = -1;
+  unsigned step_grid = 0, rebuild_grid = 0;
+  const void* step_fn = nullptr;
+  const void* rebuild_fn = nullptr;
+  std::vector<int> s_args;
+  int builds = 0, replays = 0;
+
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    njobs = most = remap = -1;
+  }
+};
+
 struct lbm_ctx {
   lbm_config cfg;
   Layout lay;
@@ -167,9 +192,11 @@ struct lbm_ctx {
   int nblocks;       // 256-lane blocks (init, exports, reductions)
   lbm_schedule sched;  // step_block, tiles, remap, rebuild workgroups (resolved)
   StepGraph graphs[2];  // by buffer parity
+  BatchGraph batch_graph;  // quanta of batches this context leads
 
   ~lbm_ctx() {
     for (auto& g : graphs) g.reset();
+    batch_graph.reset();
   }
   int step_tiles() const {
     return static_cast<int>((grid.N + sched.step_block - 1) / sched.step_block);
@@ -570,9 +597,68 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
 // batch.  dev_jobs / dev_keys: device memory for the job table and the
 // failure words (n entries each); host_jobs / host_keys: host staging of
 // the same size.
+// Records (or reuses) the graph of a quantum's launches in ctxs[0]'s
+// batch graph and replays it once.
+lbm_status replay_batch_graph(lbm_ctx* c0, JobArgs* dev_jobs, int njobs, int most,
+                              const void* step_fn, dim3 step_grid, int B, int remap,
+                              const void* rebuild_fn, dim3 rebuild_grid, bool any_rebuild) {
+  BatchGraph& G = c0->batch_graph;
+  const void* rfn = any_rebuild ? rebuild_fn : nullptr;
+  if (!G.exec || G.jobs != dev_jobs || G.njobs != njobs || G.most != most || G.B != B ||
+      G.remap != remap || G.step_grid != step_grid.x || G.rebuild_grid != rebuild_grid.x ||
+      G.step_fn != step_fn || G.rebuild_fn != rfn) {
+    G.reset();
+    if (hipGraphCreate(&G.graph, 0) != hipSuccess) return LBM_ERR_HIP;
+    G.s_args.resize(most);
+    hipGraphNode_t prev = nullptr;
+    lbm_status st = LBM_OK;
+    JobArgs* jobs = dev_jobs;
+    int nj = njobs, rm = remap;
+    for (int k = 0; k < most && st == LBM_OK; ++k) {
+      G.s_args[k] = k;
+      for (int pass = rfn ? 0 : 1; pass < 2 && st == LBM_OK; ++pass) {
+        hipKernelNodeParams p{};
+        void* rparams[] = {&jobs, &nj, &G.s_args[k]};
+        void* sparams[] = {&jobs, &nj, &G.s_args[k], &rm};
+        p.func = const_cast<void*>(pass == 0 ? rfn : step_fn);
+        p.gridDim = pass == 0 ? rebuild_grid : step_grid;
+        p.blockDim = dim3(pass == 0 ? kBlock : B);
+        p.sharedMemBytes = 0;
+        p.kernelParams = pass == 0 ? rparams : sparams;
+        p.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        if (hipGraphAddKernelNode(&node, G.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) !=
+            hipSuccess)
+          st = LBM_ERR_HIP;
+        prev = node;
+      }
+    }
+    if (st == LBM_OK && hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0) != hipSuccess)
+      st = LBM_ERR_HIP;
+    if (st != LBM_OK) {
+      G.reset();
+      return st;
+    }
+    G.jobs = dev_jobs;
+    G.njobs = njobs;
+    G.most = most;
+    G.B = B;
+    G.remap = remap;
+    G.step_grid = step_grid.x;
+    G.rebuild_grid = rebuild_grid.x;
+    G.step_fn = step_fn;
+    G.rebuild_fn = rfn;
+    G.builds += 1;
+  }
+  if (hipGraphLaunch(G.exec, c0->stream) != hipSuccess) return LBM_ERR_HIP;
+  G.replays += 1;
+  return LBM_OK;
+}
+
 lbm_status step_batched_common(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n,
                                JobArgs* dev_jobs, unsigned long long* dev_keys,
-                               JobArgs* host_jobs, unsigned long long* host_keys) {
+                               JobArgs* host_jobs, unsigned long long* host_keys,
+                               bool graph = false) {
   int32_t most = 0;
   bool any_rebuild = false;
   long long nodes = 0;
@@ -625,15 +711,21 @@ lbm_status step_batched_common(lbm_ctx* const* ctxs, const int32_t* nsteps, int3
   const dim3 rebuild_grid(static_cast<unsigned>(std::min<long long>((nodes + kBlock - 1) / kBlock, 4096)));
   const void* rebuild_batched = rebuild_batched_fn(c0->cfg.precision, c0->cfg.constraints);
   int remap = c0->sched.xcd_remap;
-  for (int32_t st = 0; st < most; ++st) {
-    int njobs = n, s_arg = st;
-    void* rebuild_params[] = {&dev_jobs, &njobs, &s_arg};
-    void* step_params[] = {&dev_jobs, &njobs, &s_arg, &remap};
-    if (any_rebuild)
-      HIP_TRY(hipLaunchKernel(rebuild_batched, rebuild_grid, dim3(kBlock), rebuild_params, 0,
-                              c0->stream));
-    HIP_TRY(hipLaunchKernel(step_fn, step_grid, dim3(B), step_params, 0, c0->stream));
-    HIP_TRY(hipGetLastError());
+  if (graph && most > 0) {
+    const lbm_status gs = replay_batch_graph(c0, dev_jobs, n, most, step_fn, step_grid, B, remap,
+                                             rebuild_batched, rebuild_grid, any_rebuild);
+    if (gs) return gs;
+  } else {
+    for (int32_t st = 0; st < most; ++st) {
+      int njobs = n, s_arg = st;
+      void* rebuild_params[] = {&dev_jobs, &njobs, &s_arg};
+      void* step_params[] = {&dev_jobs, &njobs, &s_arg, &remap};
+      if (any_rebuild)
+        HIP_TRY(hipLaunchKernel(rebuild_batched, rebuild_grid, dim3(kBlock), rebuild_params, 0,
+                                c0->stream));
+      HIP_TRY(hipLaunchKernel(step_fn, step_grid, dim3(B), step_params, 0, c0->stream));
+      HIP_TRY(hipGetLastError());
+    }
   }
   for (int32_t k = 0; k < n; ++k) {
     ctxs[k]->cur ^= (nsteps[k] & 1);
@@ -1077,6 +1169,23 @@ lbm_status lbm_step_batched(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t
                              reinterpret_cast<JobArgs*>(c0->ws + c0->lay.batch_off),
                              reinterpret_cast<unsigned long long*>(c0->ws + c0->lay.keys_off),
                              jobs.data(), keys.data());
+}
+
+lbm_status lbm_step_batched_graph(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n,
+                                  int32_t* graph_built) {
+  if (!ctxs || !nsteps || n < 0 || n > kMaxBatch || (n > 0 && !ctxs[0])) return LBM_ERR_ARG;
+  if (graph_built) *graph_built = 0;
+  if (n == 0) return LBM_OK;
+  std::vector<JobArgs> jobs(n);
+  std::vector<unsigned long long> keys(n, ~0ull);
+  lbm_ctx* c0 = ctxs[0];
+  const int before = c0->batch_graph.builds;
+  const lbm_status st =
+      step_batched_common(ctxs, nsteps, n, reinterpret_cast<JobArgs*>(c0->ws + c0->lay.batch_off),
+                          reinterpret_cast<unsigned long long*>(c0->ws + c0->lay.keys_off),
+                          jobs.data(), keys.data(), true);
+  if (graph_built) *graph_built = c0->batch_graph.builds - before;
+  return st;
 }
 
 lbm_status lbm_step_batched_noalloc(lbm_ctx* const* ctxs, const int32_t* nsteps, int32_t n) {

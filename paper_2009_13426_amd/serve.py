@@ -200,7 +200,8 @@ class GpuEngine:
     (both from the cache; `prepare` tunes the missing ones before serving,
     so that tuning never falls in served time).  None: library defaults."""
 
-    def __init__(self, precision: str = "fp32", device=None, schedule: Optional[str] = None):
+    def __init__(self, precision: str = "fp32", device=None, schedule: Optional[str] = None,
+                 graph: bool = False):
         import torch
         from . import Sim, lib, make_config, workspace_bytes, _check
         self.torch = torch
@@ -212,6 +213,8 @@ class GpuEngine:
         self.template = Sim(8, 8, device=self.device, stream=self.stream, precision=precision)
         self.auto = schedule == "auto"
         self.batch_schedule = None
+        self.graph = graph          # quanta as replays of a HIP graph (lbm_step_batched_graph)
+        self.graph_builds = self.graph_replays = 0
 
     def prepare(self, requests: Sequence[Request]):
         """Tunes (or reads from the cache) every schedule the requests need."""
@@ -249,7 +252,14 @@ class GpuEngine:
         n = len(sims)
         arr = (C.c_void_p * n)(*[s.handle.value for s in sims])
         ks = (C.c_int32 * n)(*[int(k) for k in steps])
-        st = self.lib.lbm_step_batched(arr, ks, n)
+        if self.graph:
+            built = C.c_int32(0)
+            st = self.lib.lbm_step_batched_graph(arr, ks, n, C.byref(built))
+            if st == 0:
+                self.graph_builds += built.value
+                self.graph_replays += 1 - built.value
+        else:
+            st = self.lib.lbm_step_batched(arr, ks, n)
         return batch_statuses(int(st), n, lambda k: self.lib.lbm_sync(sims[k].handle))
 
     def run_alone(self, sim, steps: int) -> int:

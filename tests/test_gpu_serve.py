@@ -116,3 +116,31 @@ def test_many_jobs_in_one_batch_equal_alone(serve):
         for key in ("rho", "ux", "uy", "T", "Ux", "Uy"):
             assert np.array_equal(got[key], want[key]), (wl.name, k, key)
         s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_graph_replayed_quanta_equal_plain_batched(serve, precision):
+    """Batched quanta replayed as a HIP graph (lbm_step_batched_graph) give
+    the populations of plain batched launches bit for bit: three quanta on
+    the same batch (recorded once, then replayed with a fresh job table),
+    then a quantum with one job fewer (the launch shape changes: recorded
+    again)."""
+    import paper_2009_13426_amd as lbm
+    wls = [W.four_quadrant(48 + 11 * k, 40, sub=k + 5) for k in range(3)] + \
+          [W.isentropic_vortex(56, steps=40)]
+    plain = [lbm.Sim.from_workload(wl, precision=precision) for wl in wls]
+    graph = [lbm.Sim.from_workload(wl, precision=precision) for wl in wls]
+    built = []
+    for q, steps in enumerate([[10, 10, 10, 10], [10, 7, 10, 4], [10, 10, 10, 10]]):
+        lbm.step_batched(plain, steps)
+        built.append(lbm.step_batched(graph, steps, graph=True))
+    lbm.step_batched(plain[:3], [6, 6, 6])
+    built.append(lbm.step_batched(graph[:3], [6, 6, 6], graph=True))
+    print(f"{precision}: graph recorded per quantum {built}", flush=True)
+    assert built == [1, 0, 0, 1]
+    for a, b in zip(plain, graph):
+        fa, ga = a.populations()
+        fb, gb = b.populations()
+        assert bool((fa == fb).all()) and bool((ga == gb).all())
+    for s in plain + graph:
+        s.close()
