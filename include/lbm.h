@@ -48,7 +48,10 @@ typedef struct lbm_ctx lbm_ctx;
 typedef enum {
   LBM_OK = 0,
   LBM_ERR_ARG = -1,          /* invalid argument or configuration */
-  LBM_ERR_WORKSPACE = -2,    /* workspace missing, too small or misaligned */
+  LBM_ERR_WORKSPACE = -2,    /* workspace missing, too small or misaligned; or, from a
+                                step, the queue of links to rebuild (4 nx ny pairs of
+                                source and lattice; 21 nx ny below 65536 nodes, which
+                                cannot fill) overflowed */
   LBM_ERR_HIP = -3,          /* a HIP runtime call failed */
   LBM_ERR_STATE = -4,        /* call out of order (e.g. step before init) */
   LBM_ERR_NEWTON = -5,       /* an equilibrium solve did not converge */
@@ -140,7 +143,8 @@ typedef struct {
 void lbm_default_config(lbm_config* cfg, int32_t nx, int32_t ny);
 
 /* Device bytes the context needs for cfg (two population buffers, lattice
- * tags, diagnostics, initial-guess table).  0 if cfg is invalid. */
+ * tags, the moments and rebuild queue carried between steps, diagnostics,
+ * initial-guess table).  0 if cfg is invalid. */
 size_t lbm_workspace_bytes(const lbm_config* cfg);
 
 /* Creates a context on the current HIP device.  dev_workspace: device

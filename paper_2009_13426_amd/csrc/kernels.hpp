@@ -66,9 +66,19 @@ struct Grid {
 struct Carry {
   unsigned* mask;      // links of the node's next pull whose source collided in another lattice
   void* mac;           // [4][N] of S: rho, u'x, u'y, T of the last collision (lattice frame)
-  int* list;           // nodes with a non-zero mask (first *count entries)
-  unsigned* counters;  // [2]: list lengths, alternating with the step parity
+  int* list;           // nodes with a non-zero mask (first counters[parity] entries)
+  unsigned* counters;  // [4]: list lengths (0, 1) and pair-queue lengths (2, 3),
+                       // alternating with the step parity
+  // D2Q21: the links to rebuild as (source node, receiver lattice) pairs,
+  // each pair once: pairs[i] = source | (lattice16 << 32), at most pair_cap
+  // entries; seen[s] marks the receiver lattices already queued for source
+  // s (bit (dUx + 3) * 7 + (dUy + 3) of the lattice difference)
+  unsigned long long* pairs;
+  unsigned long long* seen;
+  long long pair_cap;
 };
+
+enum : unsigned { kCodeQueueFull = 3 };
 
 struct StepArgs {
   const void* fin;
@@ -382,27 +392,74 @@ __device__ __forceinline__ NewtonOut solve_of(const GuessTable& tb, double ux, d
     return solve_equilibrium(tb, ux, uy, T, P.tol, P.max_iter, w);
 }
 
-// Post-collision population of velocity plane k in the receiver's lattice
-// (Lx, Ly), rebuilt at source node s by Grad's ansatz from the moments of
-// s's last collision and central differences of its neighbours' (eq.
-// GradGeneral with h* = h_eq + (1 - 1/tau) h_neq, tau = 1/2 + nu / T(s)).
+// The rebuilt links of one queued pair: source node s, receiver lattice
+// (Lx, Ly).  Every receiver r = s + c_k + (Lx, Ly) whose next pull is in
+// that lattice and whose link k is marked in its mask gets, in its own slot
+// of the buffer the coming step writes, the post-collision population of
+// plane k built by Grad's ansatz from the moments of s's last collision and
+// central differences of its neighbours' (eq. GradGeneral with h* = h_eq +
+// (1 - 1/tau) h_neq, tau = 1/2 + nu / T(s)), in the receiver's lattice at
+// the source's state.  One equilibrium solve serves all the links of the
+// pair.  Clears s's seen mask for the coming step's queue.
 template <typename S, int M, bool PR = false>
-__device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long s, int Lx, int Ly,
-                                              int k, double& rf, double& rg, int& iters) {
+__device__ __forceinline__ void rebuild_pair(const RebuildArgs& a, unsigned long long entry) {
   const CarryT<S>* mac = static_cast<const CarryT<S>*>(a.carry.mac);
   const long long N = a.grid.N;
   const int nx = a.grid.nx, ny = a.grid.ny;
   const Phys& P = a.phys;
+  const unsigned s = static_cast<unsigned>(entry & 0xFFFFFFFFull);
+  const int L16 = static_cast<int>((entry >> 32) & 0xFFFFull);
+  const int Lx = static_cast<int8_t>(L16 & 0xFF), Ly = static_cast<int8_t>((L16 >> 8) & 0xFF);
+  a.carry.seen[s] = 0ull;
+  const int ys = static_cast<int>(s / static_cast<unsigned>(nx));
+  const int xs = static_cast<int>(s - static_cast<unsigned>(ys) * static_cast<unsigned>(nx));
+  // receivers of the pair: lattice L and link k marked (their indices are
+  // recomputed at the writes rather than held across the solve)
+  const auto receiver = [&](int k, int x0, int y0) {
+    const int xr = wrapc(x0 + plane_cx(k) + Lx, nx, a.grid.fast_x);
+    const int yr = wrapc(y0 + plane_cy(k) + Ly, ny, a.grid.fast_y);
+    return static_cast<unsigned>(yr) * static_cast<unsigned>(nx) + static_cast<unsigned>(xr);
+  };
+  unsigned take = 0u;
+  {
+    int tg[kQ];
+    unsigned mk[kQ];
+    static_for<0, kQ>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const unsigned r = receiver(k, xs, ys);
+      tg[k] = a.tags[r];
+      mk[k] = a.carry.mask[r];
+    });
+    static_for<0, kQ>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      if (tag_un16(tg[k]) == L16 && ((mk[k] >> k) & 1u)) take |= 1u << k;
+    });
+    // take is settled here: the gathered tags and masks die before the solve
+    asm volatile("" : "+v"(take));
+  }
   const double rho = static_cast<double>(mac[s]);
   double ux, uy, T;
   carried_uT<CarryT<S>>(mac, a.tags, N, s, ux, uy, T);
-  rf = 0.0;
-  rg = 0.0;
-  iters = 0;
-  if (!(rho > 0.0) || !(T > 0.0) || !(rho < 1e300) || !(T < 1e300)) return kCodeNonphysical;
+  if (!(rho > 0.0) || !(T > 0.0) || !(rho < 1e300) || !(T < 1e300)) {
+    record_failure(a.diag, a.step, s, kCodeNonphysical);
+    return;
+  }
+  Weights w;
+  const NewtonOut no = solve_of<M>(a.table, ux - Lx, uy - Ly, T, P, w);
+  if (P.stats) {
+    atomicAdd(&a.diag->newton_calls, 1ull);
+    atomicAdd(&a.diag->newton_iters, static_cast<unsigned long long>(no.iters));
+    atomicAdd(&a.diag->hist[no.iters < LBM_HIST_BINS ? no.iters : LBM_HIST_BINS - 1], 1ull);
+    atomicAdd(&a.diag->mismatched, static_cast<unsigned long long>(__popc(take)));
+  }
+  if (!no.ok) {
+    record_failure(a.diag, a.step, s, kCodeNewton);
+    return;
+  }
+  // central differences of the neighbours' moments (loaded after the
+  // solve, which then has their registers)
   double du[4] = {0.0, 0.0, 0.0, 0.0}, dT[2] = {0.0, 0.0};
   if (P.nu > 0.0) {
-    const int ys = static_cast<int>(s / nx), xs = static_cast<int>(s - static_cast<long long>(ys) * nx);
     const long long xp = (long long)ys * nx + wrapc(xs + 1, nx, a.grid.fast_x);
     const long long xm = (long long)ys * nx + wrapc(xs - 1, nx, a.grid.fast_x);
     const long long yp = (long long)wrapc(ys + 1, ny, a.grid.fast_y) * nx + xs;
@@ -419,34 +476,17 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
     du[3] = 0.5 * (vyp - vym);
     dT[1] = 0.5 * (Sp - Sm);
   }
-  Weights w;
-  const NewtonOut no = solve_of<M>(a.table, ux - Lx, uy - Ly, T, P, w);
-  iters = no.iters;
-  if (!no.ok) return kCodeNewton;
-  double wk = 0.0, cxk = 0.0, cyk = 0.0;
-  static_for<0, kQ>([&](auto kc) {
-    constexpr int kk = decltype(kc)::value;
-    if (k == kk) {
-      wk = weight_of<kk>(w);
-      cxk = plane_cx(kk);
-      cyk = plane_cy(kk);
-    }
-  });
   const GradState gs = grad_state(rho, ux, uy, T, du, dT, P);
-  double phif, phig;
-  grad_phi(gs, cxk + Lx, cyk + Ly, P, phif, phig);
   const double tau = 0.5 + P.nu / T;
   const double kf = 1.0 - 1.0 / tau;
-  const double feq = rho * wk;
-  const double geq = (2.0 * P.Cv - 2.0) * T * feq;
-  rf = feq * (1.0 + kf * phif);
-  rg = geq * (1.0 + kf * phig);
+  const double gfac = (2.0 * P.Cv - 2.0) * T;
+  ShakhovCoef sc{};
+  double ks = 0.0;
   if constexpr (PR) {
     // eq. (Shakhov) applied to the Grad populations h = h_eq (1 + phi) of
     // the source (App. E): their heat flux in the receiver's frame, then
-    // the link's share of the term
+    // each link's share of the term
     const double upx = ux - Lx, upy = uy - Ly;
-    const double gf = (2.0 * P.Cv - 2.0) * T;
     double qx = 0.0, qy = 0.0;
     static_for<0, kQ>([&](auto kc) {
       constexpr int kk = decltype(kc)::value;
@@ -454,25 +494,44 @@ __device__ __forceinline__ unsigned rebuild_link(const RebuildArgs& a, long long
       grad_phi(gs, static_cast<double>(plane_cx(kk) + Lx), static_cast<double>(plane_cy(kk) + Ly),
                P, pf, pg);
       const double fe = rho * weight_of<kk>(w);
-      const double hf = fe * (1.0 + pf), hg = gf * fe * (1.0 + pg);
+      const double hf = fe * (1.0 + pf), hg = gfac * fe * (1.0 + pg);
       const double cx = plane_cx(kk) - upx, cy = plane_cy(kk) - upy;
       const double e = (cx * cx + cy * cy) * hf + hg;
       qx = __builtin_fma(0.5 * cx, e, qx);
       qy = __builtin_fma(0.5 * cy, e, qy);
     });
-    const ShakhovCoef sc = shakhov_coef([&](auto kc) { return weight_of<decltype(kc)::value>(w); },
-                                        rho, upx, upy, T, qx, qy, P);
+    sc = shakhov_coef([&](auto kc) { return weight_of<decltype(kc)::value>(w); }, rho, upx, upy,
+                      T, qx, qy, P);
     const double tpr = 0.5 + (tau - 0.5) * P.inv_pr;
-    const double ks = 1.0 / tau - 1.0 / tpr;
-    double sf = 0.0, sg = 0.0;
-    static_for<0, kQ>([&](auto kc) {
-      constexpr int kk = decltype(kc)::value;
-      if (k == kk) shakhov_phi<plane_cx(kk), plane_cy(kk)>(sc, sf, sg);
-    });
-    rf += ks * feq * sf;
-    rg += ks * geq * sg;
+    ks = 1.0 / tau - 1.0 / tpr;
   }
-  return 0;
+  S* fout = static_cast<S*>(a.fout);
+  S* gout = static_cast<S*>(a.gout);
+  // an opaque copy of the source's position: the compiler would otherwise
+  // keep the gather's receiver indices alive (spilled) across the solve
+  int xw = xs, yw = ys;
+  asm volatile("" : "+v"(xw), "+v"(yw));
+  static_for<0, kQ>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if ((take >> k) & 1u) {
+      double phif, phig;
+      grad_phi(gs, static_cast<double>(plane_cx(k) + Lx), static_cast<double>(plane_cy(k) + Ly), P,
+               phif, phig);
+      const double feq = rho * weight_of<k>(w);
+      const double geq = gfac * feq;
+      double rf = feq * (1.0 + kf * phif);
+      double rg = geq * (1.0 + kf * phig);
+      if constexpr (PR) {
+        double sf, sg;
+        shakhov_phi<plane_cx(k), plane_cy(k)>(sc, sf, sg);
+        rf += ks * feq * sf;
+        rg += ks * geq * sg;
+      }
+      const unsigned r = receiver(k, xw, yw);
+      plane_at(fout + k * N, r) = static_cast<S>(rf);
+      plane_at(gout + k * N, r) = static_cast<S>(rg);
+    }
+  });
 }
 
 // Relaxation-time factor alpha of the kinetic sensor eps = (1/V) sum_i
@@ -508,6 +567,78 @@ struct PullMap {
     return static_cast<unsigned>(row[plane_cy(k) + 3] + col[plane_cx(k) + 3]);
   }
 };
+
+// Lattice difference dU (receiver minus source) as a bit of the source's
+// seen mask; -1 outside [-3, 3]^2 (such pairs are queued without the check:
+// a duplicate pair writes the same values twice).
+__device__ __forceinline__ int seen_bit(int dux, int duy) {
+  return (dux >= -3 && dux <= 3 && duy >= -3 && duy <= 3) ? (dux + 3) * 7 + (duy + 3) : -1;
+}
+
+__device__ __forceinline__ unsigned long long pair_entry(unsigned s, int Lx, int Ly) {
+  return static_cast<unsigned long long>(s) |
+         (static_cast<unsigned long long>((Lx & 0xFF) | ((Ly & 0xFF) << 8)) << 32);
+}
+
+// For every set link k of receiver (x, y)'s pull mask (its lattice (Lx,
+// Ly)): source s_k = (x, y) - c_k - (Lx, Ly); the pair (s_k, lattice) joins
+// the queue unless the source's seen mask already holds the lattice.  tags:
+// the step's input tags (the Un half of a source is the lattice it
+// collided in).  Every lane of the wave calls this: one queue atomic per
+// wave (a single counter takes every append, so appends are gathered);
+// lanes with an empty mask only take part in the wave's prefix sum.
+__device__ __forceinline__ void queue_pairs(const Carry& carry, const Grid& grid, const int* tags,
+                                            int step, DevDiag* diag, int x, int y, int Lx,
+                                            int Ly, unsigned mask) {
+  PullMap pm;
+  if (mask) pm.build(x, y, Lx, Ly, grid);
+  // mark the lattice in each source's seen mask (returning atomics, all in
+  // flight before the first result is used); fresh: the links whose pair
+  // this receiver saw first
+  unsigned long long old[kQ];
+  int bit[kQ];
+  static_for<0, kQ>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    bit[k] = -1;
+    old[k] = 0ull;
+    if ((mask >> k) & 1u) {
+      const unsigned sidx = pm.template source<k>();
+      const int t = tags[sidx];
+      bit[k] = seen_bit(Lx - tag_unx(t), Ly - tag_uny(t));
+      if (bit[k] >= 0) old[k] = atomicOr(&carry.seen[sidx], 1ull << bit[k]);
+    }
+  });
+  unsigned fresh = 0u;
+  static_for<0, kQ>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (((mask >> k) & 1u) && (bit[k] < 0 || !((old[k] >> bit[k]) & 1ull))) fresh |= 1u << k;
+  });
+  // wave prefix sum of the append counts, one atomic for the wave
+  const int lane = threadIdx.x & 63;
+  const unsigned cnt = static_cast<unsigned>(__popc(fresh));
+  unsigned incl = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  const unsigned total = __shfl(incl, 63, 64);
+  if (total == 0u) return;
+  unsigned base = 0u;
+  if (lane == 0) base = atomicAdd(&carry.counters[2 + (step & 1)], total);
+  long long i = static_cast<long long>(__shfl(base, 0, 64)) + (incl - cnt);
+  static_for<0, kQ>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if ((fresh >> k) & 1u) {
+      const unsigned sidx = pm.template source<k>();
+      if (i < carry.pair_cap)
+        carry.pairs[i] = pair_entry(sidx, Lx, Ly);
+      else
+        record_failure(diag, step, sidx, kCodeQueueFull);
+      ++i;
+    }
+  });
+}
 
 // ------------------------------------------------------------ fused step
 // One node per lane; BLOCK lanes per workgroup.  The pulled populations are
@@ -825,109 +956,52 @@ void step_kernel(StepArgs a) {
 }
 
 // ------------------------------------------------------------ rebuild
-// kChunk receivers per wave and pass: a receiver has up to 21 links, so
-// small chunks spread the items over many waves.
-constexpr int kChunk = 16;
-
-// One wave's chunk of a receiver list: receivers [base, base + kChunk) of
-// the count listed, their links expanded into (receiver, link) items with a
-// wave prefix sum and handed out one per lane through the wave's LDS rows
-// (wave-uniform arguments; every lane of the wave takes part).
-template <typename S, int M, bool PR = false>
-__device__ __forceinline__ void rebuild_chunk(const RebuildArgs& a, unsigned count,
-                                              long long base, int* sh_node, int* sh_k) {
-  const int lane = threadIdx.x & 63;
-  const Phys& P = a.phys;
-  const long long N = a.grid.N;
-  const int nx = a.grid.nx;
-  S* fout = static_cast<S*>(a.fout);
-  S* gout = static_cast<S*>(a.gout);
-  const long long i = base + lane;
-  int node = 0;
-  unsigned msk = 0u;
-  if (lane < kChunk && i < count) {
-    node = a.carry.list[i];
-    msk = a.carry.mask[node];
+// a2 in two launches before a step.  queue: every receiver of the list the
+// previous step wrote turns its marked links into (source, receiver
+// lattice) pairs, each pair queued once; it also clears the other list
+// counter for the coming step's appends.  rebuild: one lane per queued
+// pair (rebuild_pair), grid-stride, clearing the other queue counter.
+// Entry i of a receiver list of `count` (i past the end: an empty mask,
+// the lane only joins the wave's ballots).
+__device__ __forceinline__ void queue_entry(const Carry& carry, const Grid& grid, const int* tags,
+                                            int step, DevDiag* diag, int max_shift, long long i,
+                                            unsigned count) {
+  int x = 0, y = 0, Lx = 0, Ly = 0;
+  unsigned mask = 0u;
+  if (i < count) {
+    const int r = carry.list[i];
+    mask = carry.mask[r];
+    const int t = tags[r];
+    Lx = min(max(tag_unx(t), -max_shift), max_shift);
+    Ly = min(max(tag_uny(t), -max_shift), max_shift);
+    y = r / grid.nx;
+    x = r - y * grid.nx;
   }
-  // exclusive prefix of the link counts over the wave
-  const int cnt = __popc(msk);
-  int v = cnt;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
-  const int total = __shfl(v, 63, 64);
-  const int off = v - cnt;
-  for (int r0 = 0; r0 < total; r0 += 64) {
-    // scatter this round's items to their lanes
-    if (cnt > 0 && off < r0 + 64 && off + cnt > r0) {
-      int j = off;
-      unsigned m = msk;
-      while (m) {
-        const int k = __ffs(m) - 1;
-        m &= m - 1u;
-        if (j >= r0 && j < r0 + 64) {
-          sh_node[j - r0] = node;
-          sh_k[j - r0] = k;
-        }
-        ++j;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (r0 + lane < total) {
-      const int xn = sh_node[lane];
-      const int k = sh_k[lane];
-      const int t = a.tags[xn];
-      const int Lx = min(max(tag_unx(t), -P.max_abs_shift), P.max_abs_shift);
-      const int Ly = min(max(tag_uny(t), -P.max_abs_shift), P.max_abs_shift);
-      const int yx = xn / nx, xx = xn - yx * nx;
-      int cx = 0, cy = 0;
-      static_for<0, kQ>([&](auto kc) {
-        constexpr int kk = decltype(kc)::value;
-        if (k == kk) {
-          cx = plane_cx(kk);
-          cy = plane_cy(kk);
-        }
-      });
-      const long long s = static_cast<long long>(wrapc(yx - (cy + Ly), a.grid.ny, a.grid.fast_y)) * nx +
-                          wrapc(xx - (cx + Lx), nx, a.grid.fast_x);
-      double rf, rg;
-      int it;
-      const unsigned code = rebuild_link<S, M, PR>(a, s, Lx, Ly, k, rf, rg, it);
-      if (code) record_failure(a.diag, a.step, s, code);
-      plane_at(fout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rf);
-      plane_at(gout + k * N, static_cast<unsigned>(xn)) = static_cast<S>(rg);
-      if (P.stats) {
-        atomicAdd(&a.diag->mismatched, 1ull);
-        atomicAdd(&a.diag->newton_calls, 1ull);
-        atomicAdd(&a.diag->newton_iters, static_cast<unsigned long long>(it));
-        atomicAdd(&a.diag->hist[it < LBM_HIST_BINS ? it : LBM_HIST_BINS - 1], 1ull);
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
+  queue_pairs(carry, grid, tags, step, diag, x, y, Lx, Ly, mask);
 }
 
-// a2: rebuilds, before a step, every link of that step's pull whose source
-// collided in another lattice, into the receiver's slot of the buffer the
-// step writes.  The list holds the receivers; grid-stride over its chunks.
-// Clears the other list counter for the coming step's appends.
+__device__ __forceinline__ void queue_body(const RebuildArgs& a, long long i0, long long stride) {
+  const unsigned count = a.carry.counters[(a.step - 1) & 1];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.carry.counters[a.step & 1] = 0u;
+  // whole waves go round the loop together (the queue uses wave ballots)
+  const long long n = (static_cast<long long>(count) + 63) / 64 * 64;
+  for (long long i = i0; i < n; i += stride)
+    queue_entry(a.carry, a.grid, a.tags, a.step, a.diag, a.phys.max_abs_shift, i, count);
+}
+
+__global__ __launch_bounds__(kBlock) void queue_kernel(RebuildArgs a) {
+  queue_body(a, static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x,
+             static_cast<long long>(gridDim.x) * kBlock);
+}
+
 template <typename S, int M, bool PR = false>
 __device__ __forceinline__ void rebuild_body(const RebuildArgs& a) {
-  __shared__ int sh_node[kWaves][64];
-  __shared__ int sh_k[kWaves][64];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const unsigned count = a.carry.counters[(a.step - 1) & 1];
-  if (blockIdx.x == 0 && tid == 0) a.carry.counters[a.step & 1] = 0u;
-  const long long waves = static_cast<long long>(gridDim.x) * kWaves;
-  for (long long base = (static_cast<long long>(blockIdx.x) * kWaves + wave) * kChunk; base < count;
-       base += waves * kChunk)
-    rebuild_chunk<S, M, PR>(a, count, base, sh_node[wave], sh_k[wave]);
+  const unsigned count = a.carry.counters[2 + (a.step & 1)];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.carry.counters[2 + ((a.step + 1) & 1)] = 0u;
+  const long long n = min(static_cast<long long>(count), a.carry.pair_cap);
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride)
+    rebuild_pair<S, M, PR>(a, a.carry.pairs[i]);
 }
 
 template <typename S, int M = kM, bool PR = false>
@@ -1002,22 +1076,16 @@ __global__ __launch_bounds__(kBlock) void gather_fail_keys_kernel(const JobArgs*
   if (k < njobs) out[k] = jobs[k].diag->fail_key;
 }
 
-// Rebuilds of step s for every job of a batch as one flat index space: the
-// chunks of every job's receiver list, numbered job after job (a block-wide
-// prefix sum over the jobs' chunk counts in LDS), grid-stride over the
-// waves; a wave finds its chunk's job by binary search.  Small jobs no
-// longer leave the grid idle while each job's list is taken in turn.
 constexpr int kMaxJobs = 1024;
 
-template <typename S, int M = kM>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
-void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
-  __shared__ int sh_node[kWaves][64];
-  __shared__ int sh_k[kWaves][64];
-  __shared__ unsigned sh_first[kMaxJobs + 1];  // first global chunk of each job
-  __shared__ unsigned sh_part[kBlock];
-  const int tid = threadIdx.x, wave = tid >> 6;
-  // chunk counts of the (up to four) jobs of this thread, then a block scan
+// Exclusive prefix over a batch's jobs of count(job, step) for step s (0 for
+// a job past its steps or on a fixed lattice), a block-wide scan in LDS:
+// sh_first[k] for job k, sh_first[kMaxJobs] the total, which it returns.
+// Every lane of the block calls it.
+template <typename F>
+__device__ __forceinline__ unsigned job_prefix(const JobArgs* jobs, int njobs, int s, F count,
+                                               unsigned* sh_first, unsigned* sh_part) {
+  const int tid = threadIdx.x;
   constexpr int kPer = kMaxJobs / kBlock;
   unsigned local[kPer], sum = 0;
 #pragma unroll
@@ -1026,12 +1094,7 @@ void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
     unsigned c = 0;
     if (k < njobs) {
       const JobArgs& j = jobs[k];
-      if (s < j.nsteps && j.phys.shift_mode != 1) {
-        const int step = j.step0 + s + 1;
-        const unsigned count = j.carry.counters[(step - 1) & 1];
-        c = (count + kChunk - 1) / kChunk;
-        if (blockIdx.x == 0) j.carry.counters[step & 1] = 0u;
-      }
+      if (s < j.nsteps && j.phys.shift_mode != 1) c = count(j, j.step0 + s + 1);
     }
     local[q] = c;
     sum += c;
@@ -1052,16 +1115,70 @@ void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
   }
   if (tid == kBlock - 1) sh_first[kMaxJobs] = sh_part[kBlock - 1];
   __syncthreads();
-  const unsigned total = sh_first[kMaxJobs];
-  const unsigned waves = gridDim.x * kWaves;
-  for (unsigned g = blockIdx.x * kWaves + wave; g < total; g += waves) {
-    // last job whose first chunk is <= g (jobs without chunks are skipped:
-    // their first equals the next job's)
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (sh_first[mid] <= g) lo = mid; else hi = mid - 1;
-    }
+  return sh_first[kMaxJobs];
+}
+
+// Last job whose first item is <= g (jobs with no items are skipped: their
+// first equals the next job's).
+__device__ __forceinline__ int job_of(const unsigned* sh_first, int njobs, unsigned g) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sh_first[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The queue pass of step s for every job of a batch: the jobs' receiver
+// lists cut into waves of 64 entries, numbered job after job, grid-stride
+// over the waves (a wave works on one job, as the pair appends need).
+__global__ __launch_bounds__(kBlock) void queue_batched_kernel(const JobArgs* jobs, int njobs,
+                                                               int s) {
+  __shared__ unsigned sh_first[kMaxJobs + 1];  // first wave of each job
+  __shared__ unsigned sh_part[kBlock];
+  const unsigned total = job_prefix(
+      jobs, njobs, s,
+      [](const JobArgs& j, int step) {
+        const unsigned c = j.carry.counters[(step - 1) & 1];
+        if (blockIdx.x == 0) j.carry.counters[step & 1] = 0u;
+        return (c + 63u) / 64u;
+      },
+      sh_first, sh_part);
+  constexpr unsigned kWaves = kBlock / 64;
+  const unsigned lane = threadIdx.x & 63;
+  for (unsigned w = blockIdx.x * kWaves + threadIdx.x / 64; w < total; w += gridDim.x * kWaves) {
+    const int jb = job_of(sh_first, njobs, w);
+    const JobArgs& j = jobs[jb];
+    const int step = j.step0 + s + 1;
+    const int src = (j.cur + s) & 1;
+    const unsigned count = j.carry.counters[(step - 1) & 1];
+    const long long i = static_cast<long long>(w - sh_first[jb]) * 64 + lane;
+    queue_entry(j.carry, j.grid, j.tag[src], step, j.diag, j.phys.max_abs_shift, i, count);
+  }
+}
+
+// Rebuilds of step s for every job of a batch as one flat index space: the
+// queued (source, lattice) pairs of every job, numbered job after job,
+// grid-stride over the lanes; a lane finds its pair's job by binary search.
+// Small jobs do not leave the grid idle while each job's queue is taken in
+// turn.
+template <typename S, int M = kM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES_PER_EU)))
+void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
+  __shared__ unsigned sh_first[kMaxJobs + 1];  // first global pair of each job
+  __shared__ unsigned sh_part[kBlock];
+  const unsigned total = job_prefix(
+      jobs, njobs, s,
+      [](const JobArgs& j, int step) {
+        const unsigned c = static_cast<unsigned>(
+            min(static_cast<long long>(j.carry.counters[2 + (step & 1)]), j.carry.pair_cap));
+        if (blockIdx.x == 0) j.carry.counters[2 + ((step + 1) & 1)] = 0u;
+        return c;
+      },
+      sh_first, sh_part);
+  const unsigned lanes = gridDim.x * kBlock;
+  for (unsigned g = blockIdx.x * kBlock + threadIdx.x; g < total; g += lanes) {
+    const int lo = job_of(sh_first, njobs, g);
     const JobArgs& j = jobs[lo];
     const int src = (j.cur + s) & 1, dst = src ^ 1;
     RebuildArgs a;
@@ -1074,9 +1191,7 @@ void rebuild_batched_kernel(const JobArgs* jobs, int njobs, int s) {
     a.table = j.table;
     a.step = j.step0 + s + 1;
     a.diag = j.diag;
-    const unsigned count = j.carry.counters[(a.step - 1) & 1];
-    const long long base = static_cast<long long>(g - sh_first[lo]) * kChunk;
-    rebuild_chunk<S, M>(a, count, base, sh_node[wave], sh_k[wave]);
+    rebuild_pair<S, M>(a, j.carry.pairs[g - sh_first[lo]]);
   }
 }
 

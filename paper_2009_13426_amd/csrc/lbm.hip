@@ -60,6 +60,8 @@ struct Layout {
   size_t diag_off, part_off, sums_off, table_off, total;
   size_t off_pop[2], off_tag[2];
   size_t mac_off, mask_off, list_off, count_off;  // carried from step to step
+  size_t seen_off, pair_off;                      // the rebuild queue (D2Q21)
+  long long pair_cap;
   size_t batch_off;                               // job table of a batched call
   size_t keys_off;                                // failure words of a batched call
   int nparts;
@@ -110,7 +112,16 @@ Layout layout(const lbm_config* c) {
   L.list_off = off;
   off += align_up(N * sizeof(int));
   L.count_off = off;
-  off += align_up(2 * sizeof(unsigned));
+  off += align_up(4 * sizeof(unsigned));  // list and pair-queue lengths
+  // rebuild queue: a seen mask per node and room for the (source, lattice)
+  // pairs: 21 N on grids below 65536 nodes (a pair per link at most, so it
+  // cannot fill), else 4 N (four pairs per node on average; the flows here
+  // queue about 0.01-0.05 per node)
+  L.seen_off = off;
+  off += align_up(N * sizeof(unsigned long long));
+  L.pair_cap = static_cast<long long>(N < 65536 ? 21 * N : 4 * N);
+  L.pair_off = off;
+  off += align_up(static_cast<size_t>(L.pair_cap) * sizeof(unsigned long long));
   L.batch_off = off;
   off += align_up(kMaxBatch * sizeof(JobArgs));
   L.keys_off = off;
@@ -214,6 +225,9 @@ struct lbm_ctx {
     k.mac = ws + lay.mac_off;
     k.list = reinterpret_cast<int*>(ws + lay.list_off);
     k.counters = reinterpret_cast<unsigned*>(ws + lay.count_off);
+    k.seen = reinterpret_cast<unsigned long long*>(ws + lay.seen_off);
+    k.pairs = reinterpret_cast<unsigned long long*>(ws + lay.pair_off);
+    k.pair_cap = lay.pair_cap;
     return k;
   }
   DevDiag* diag() const { return reinterpret_cast<DevDiag*>(ws + lay.diag_off); }
@@ -229,13 +243,13 @@ struct lbm_ctx {
 namespace {
 
 // Device-side clean diagnostics record (fail_key = ~0, counters 0) and
-// empty rebuild lists.
+// empty rebuild lists and queues.
 __global__ void diag_reset_kernel(DevDiag* d, unsigned* list_counters) {
   const int i = threadIdx.x;
   unsigned long long* w = reinterpret_cast<unsigned long long*>(d);
   const int n = static_cast<int>(sizeof(DevDiag) / sizeof(unsigned long long));
   if (i < n) w[i] = (i == 0) ? ~0ull : 0ull;
-  if (i < 2) list_counters[i] = 0u;
+  if (i < 4) list_counters[i] = 0u;
 }
 
 // Device entry of the step kernel for a storage type, pass and block size;
@@ -394,8 +408,9 @@ Launch<StepArgs> step_launch(const lbm_ctx* c, int src, int dst, bool stream_pas
 }
 
 // Rebuilds the mismatched links of step `step` (pulling from buffer src)
-// into buffer dst.  No launch (fn nullptr) with one lattice for all nodes.
-Launch<RebuildArgs> rebuild_launch(const lbm_ctx* c, int src, int dst, int step) {
+// into buffer dst: the queue pass (queue = true), then the rebuild pass.
+// No launch (fn nullptr) with one lattice for all nodes.
+Launch<RebuildArgs> rebuild_launch(const lbm_ctx* c, int src, int dst, int step, bool queue) {
   Launch<RebuildArgs> L;
   if (c->cfg.shift_mode == LBM_SHIFT_FIXED) return L;
   RebuildArgs& a = L.args;
@@ -408,7 +423,11 @@ Launch<RebuildArgs> rebuild_launch(const lbm_ctx* c, int src, int dst, int step)
   a.table = c->table;
   a.step = step;
   a.diag = c->diag();
-  L.fn = rebuild_fn(c->cfg.precision, c->cfg.constraints, shakhov_on(&c->cfg));
+  // the 49-velocity rebuild takes its receiver list directly
+  if (queue)
+    L.fn = c->cfg.constraints == kM13 ? nullptr : reinterpret_cast<const void*>(&queue_kernel);
+  else
+    L.fn = rebuild_fn(c->cfg.precision, c->cfg.constraints, shakhov_on(&c->cfg));
   L.grid = dim3(static_cast<unsigned>(c->sched.rebuild_blocks));
   L.block = dim3(kBlock);
   return L;
@@ -430,7 +449,8 @@ lbm_status launch_step(lbm_ctx* c, int src, int dst, bool stream_pass, int step)
 }
 
 lbm_status launch_rebuild(lbm_ctx* c, int src, int dst, int step) {
-  return enqueue(rebuild_launch(c, src, dst, step), c->stream);
+  const lbm_status st = enqueue(rebuild_launch(c, src, dst, step, true), c->stream);
+  return st ? st : enqueue(rebuild_launch(c, src, dst, step, false), c->stream);
 }
 
 __global__ void set_step_base_kernel(DevDiag* d, unsigned long long base) {
@@ -466,17 +486,19 @@ lbm_status build_graph(lbm_ctx* c, int chunk, StepGraph& G) {
   G.reset();
   const int parity = static_cast<int>(c->steps_done & 1);
   G.step_args.reserve(chunk);
-  G.rebuild_args.reserve(chunk);
+  G.rebuild_args.reserve(2 * chunk);
   if (hipGraphCreate(&G.graph, 0) != hipSuccess) return LBM_ERR_HIP;
   hipGraphNode_t prev = nullptr;
   int cur = c->cur;
   lbm_status st = LBM_OK;
   for (int k = 1; k <= chunk && st == LBM_OK; ++k) {
     const int src = cur, dst = 1 - cur;
-    const Launch<RebuildArgs> R = rebuild_launch(c, src, dst, parity + k);
-    if (R.fn) {
-      G.rebuild_args.push_back(R.args);
-      st = add_node(G.graph, &prev, R, &G.rebuild_args.back());
+    for (int pass = 0; pass < 2 && st == LBM_OK; ++pass) {
+      const Launch<RebuildArgs> R = rebuild_launch(c, src, dst, parity + k, pass == 0);
+      if (R.fn) {
+        G.rebuild_args.push_back(R.args);
+        st = add_node(G.graph, &prev, R, &G.rebuild_args.back());
+      }
     }
     const Launch<StepArgs> S = step_launch(c, src, dst, true, parity + k);
     if (st == LBM_OK && !S.fn) st = LBM_ERR_ARG;
@@ -541,6 +563,14 @@ bool schedule_ok(const lbm_ctx* c, const lbm_schedule* s) {
          s->rebuild_blocks <= 65535;
 }
 
+// Status of a recorded failure word's code.
+lbm_status status_of_code(unsigned long long key) {
+  const unsigned code = static_cast<unsigned>(key & 7ull);
+  if (code == kCodeNewton) return LBM_ERR_NEWTON;
+  if (code == kCodeQueueFull) return LBM_ERR_WORKSPACE;
+  return LBM_ERR_NONPHYSICAL;
+}
+
 lbm_status read_status(lbm_ctx* c, unsigned long long* key_out) {
   unsigned long long key = ~0ull;
   HIP_TRY(hipMemcpyAsync(&key, &c->diag()->fail_key, sizeof key, hipMemcpyDeviceToHost,
@@ -548,7 +578,7 @@ lbm_status read_status(lbm_ctx* c, unsigned long long* key_out) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (key_out) *key_out = key;
   if (key == ~0ull) return LBM_OK;
-  return (key & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
+  return status_of_code(key);
 }
 
 lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const double* uy,
@@ -557,6 +587,8 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
   if (c->cfg.shift_mode == LBM_SHIFT_STATIC && (!sux || !suy)) return LBM_ERR_ARG;
   hipLaunchKernelGGL(diag_reset_kernel, dim3(1), dim3(64), 0, c->stream, c->diag(),
                      c->carry().counters);
+  HIP_TRY(hipMemsetAsync(c->ws + c->lay.seen_off, 0,
+                         static_cast<size_t>(c->grid.N) * sizeof(unsigned long long), c->stream));
   InitArgs a;
   a.rho = rho;
   a.ux = ux;
@@ -593,8 +625,8 @@ lbm_status init_common(lbm_ctx* c, const double* rho, const double* ux, const do
   return st;
 }
 
-// One rebuild launch and one step launch per step for every context of a
-// batch.  dev_jobs / dev_keys: device memory for the job table and the
+// One queue launch, one rebuild launch and one step launch per step for
+// every context of a batch.  dev_jobs / dev_keys: device memory for the job table and the
 // failure words (n entries each); host_jobs / host_keys: host staging of
 // the same size.
 // Records (or reuses) the graph of a quantum's launches in ctxs[0]'s
@@ -616,15 +648,18 @@ lbm_status replay_batch_graph(lbm_ctx* c0, JobArgs* dev_jobs, int njobs, int mos
     int nj = njobs, rm = remap;
     for (int k = 0; k < most && st == LBM_OK; ++k) {
       G.s_args[k] = k;
-      for (int pass = rfn ? 0 : 1; pass < 2 && st == LBM_OK; ++pass) {
+      // queue, rebuild, step
+      for (int pass = rfn ? 0 : 2; pass < 3 && st == LBM_OK; ++pass) {
         hipKernelNodeParams p{};
         void* rparams[] = {&jobs, &nj, &G.s_args[k]};
         void* sparams[] = {&jobs, &nj, &G.s_args[k], &rm};
-        p.func = const_cast<void*>(pass == 0 ? rfn : step_fn);
-        p.gridDim = pass == 0 ? rebuild_grid : step_grid;
-        p.blockDim = dim3(pass == 0 ? kBlock : B);
+        p.func = pass == 0   ? reinterpret_cast<void*>(&queue_batched_kernel)
+                 : pass == 1 ? const_cast<void*>(rfn)
+                             : const_cast<void*>(step_fn);
+        p.gridDim = pass < 2 ? rebuild_grid : step_grid;
+        p.blockDim = dim3(pass < 2 ? kBlock : B);
         p.sharedMemBytes = 0;
-        p.kernelParams = pass == 0 ? rparams : sparams;
+        p.kernelParams = pass < 2 ? rparams : sparams;
         p.extra = nullptr;
         hipGraphNode_t node = nullptr;
         if (hipGraphAddKernelNode(&node, G.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) !=
@@ -720,9 +755,12 @@ lbm_status step_batched_common(lbm_ctx* const* ctxs, const int32_t* nsteps, int3
       int njobs = n, s_arg = st;
       void* rebuild_params[] = {&dev_jobs, &njobs, &s_arg};
       void* step_params[] = {&dev_jobs, &njobs, &s_arg, &remap};
-      if (any_rebuild)
+      if (any_rebuild) {
+        HIP_TRY(hipLaunchKernel(reinterpret_cast<const void*>(&queue_batched_kernel), rebuild_grid,
+                                dim3(kBlock), rebuild_params, 0, c0->stream));
         HIP_TRY(hipLaunchKernel(rebuild_batched, rebuild_grid, dim3(kBlock), rebuild_params, 0,
                                 c0->stream));
+      }
       HIP_TRY(hipLaunchKernel(step_fn, step_grid, dim3(B), step_params, 0, c0->stream));
       HIP_TRY(hipGetLastError());
     }
@@ -739,8 +777,7 @@ lbm_status step_batched_common(lbm_ctx* const* ctxs, const int32_t* nsteps, int3
                          hipMemcpyDeviceToHost, c0->stream));
   HIP_TRY(hipStreamSynchronize(c0->stream));
   for (int32_t k = 0; k < n; ++k)
-    if (host_keys[k] != ~0ull)
-      return (host_keys[k] & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
+    if (host_keys[k] != ~0ull) return status_of_code(host_keys[k]);
   return LBM_OK;
 }
 
@@ -1147,7 +1184,7 @@ lbm_status lbm_get_diag(lbm_ctx* c, lbm_diag* out) {
     out->fail_step = -1;
     out->fail_node = -1;
   } else {
-    out->status = (d.fail_key & 7ull) == kCodeNewton ? LBM_ERR_NEWTON : LBM_ERR_NONPHYSICAL;
+    out->status = status_of_code(d.fail_key);
     out->fail_step = static_cast<int32_t>(d.fail_key >> 34);
     out->fail_node = static_cast<int64_t>((d.fail_key >> 3) & ((1ull << 31) - 1));
   }
