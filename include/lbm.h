@@ -108,6 +108,15 @@ typedef struct {
                                 kappa = rho Cp nu / Pr in the Grad rebuild.  8 or 13
                                 constraints, no neighbourhood choice, default schedule,
                                 not in lbm_step_batched */
+  int32_t fallback;          /* 0 (default): a state whose 8-moment equilibrium has no
+                                solution stops the run with LBM_ERR_NEWTON; 1: that
+                                collision or rebuilt link takes the four-constraint
+                                equilibrium of the same state instead, eq.
+                                (feqNum_4Mom), solved from the lattice Maxwellian with
+                                backtracking (the paper leaves the case open; it
+                                arises at rebuilt links whose source moves at |u'| ~
+                                1.6 in the receiver's lattice).  Counted in
+                                lbm_diag.fallback_solves.  8 constraints and BGK only */
 } lbm_config;
 
 typedef struct {
@@ -120,6 +129,9 @@ typedef struct {
   int64_t mismatched_links;  /* links rebuilt by Grad's ansatz */
   int64_t iter_hist[LBM_HIST_BINS];
   double conserved[4];       /* mass, x/y momentum, total energy of the current state */
+  int64_t fallback_solves;   /* collisions and rebuilt links (each link counted) that
+                                took the four-constraint equilibrium
+                                (lbm_config.fallback), initial condition included */
 } lbm_diag;
 
 /* Launch schedule of a context's step loop.  Changing it changes how the
@@ -139,7 +151,7 @@ typedef struct {
 /* Fills cfg with the defaults used by the paper's tests: gamma 1.4, nu 0,
  * adaptive shifts with half-width 0.5, Newton tolerance 1e-12 and 30
  * iterations, |U| <= 6, FP64, no sensor, no counters, 8 constraints,
- * Prandtl number 1. */
+ * Prandtl number 1, no fallback equilibrium. */
 void lbm_default_config(lbm_config* cfg, int32_t nx, int32_t ny);
 
 /* Device bytes the context needs for cfg (two population buffers, lattice

@@ -29,13 +29,13 @@ class Params(C.Structure):
                 ("fixed_uy", C.c_int), ("halfwidth", C.c_double),
                 ("newton_tol", C.c_double), ("newton_max_iter", C.c_int),
                 ("max_abs_shift", C.c_int), ("sensor", C.c_int), ("constraints", C.c_int),
-                ("prandtl", C.c_double)]
+                ("prandtl", C.c_double), ("fallback", C.c_int)]
 
 
 class Stats(C.Structure):
     _fields_ = [("newton_calls", C.c_long), ("newton_iters", C.c_long),
                 ("mismatched_links", C.c_long), ("hist", C.c_long * HIST),
-                ("fail_node", C.c_long), ("steps", C.c_long)]
+                ("fail_node", C.c_long), ("steps", C.c_long), ("fallbacks", C.c_long)]
 
 
 _lib = None
@@ -147,9 +147,10 @@ def sensor_alpha(eps):
 
 def make_params(nx, ny, gamma=1.4, nu=1e-3, shift_mode=0, fixed_U=(0, 0),
                 halfwidth=0.5, newton_tol=1e-12, newton_max_iter=100,
-                max_abs_shift=6, sensor=0, constraints=8, prandtl=1.0) -> Params:
+                max_abs_shift=6, sensor=0, constraints=8, prandtl=1.0, fallback=0) -> Params:
     return Params(nx, ny, gamma, nu, shift_mode, fixed_U[0], fixed_U[1], halfwidth,
-                  newton_tol, newton_max_iter, max_abs_shift, sensor, constraints, prandtl)
+                  newton_tol, newton_max_iter, max_abs_shift, sensor, constraints, prandtl,
+                  int(fallback))
 
 
 def grad_populations(params: Params, rho, ux, uy, T, du, dT, L, post):
@@ -183,7 +184,8 @@ class Sim:
     @classmethod
     def from_workload(cls, wl, **over):
         kw = dict(gamma=wl.gamma, nu=wl.nu, shift_mode=wl.shift_mode,
-                  fixed_U=wl.fixed_U, halfwidth=wl.halfwidth, sensor=wl.sensor)
+                  fixed_U=wl.fixed_U, halfwidth=wl.halfwidth, sensor=wl.sensor,
+                  fallback=getattr(wl, "fallback", 0))
         kw.update(over)
         s = cls(wl.nx, wl.ny, **kw)
         if kw["shift_mode"] == 2:
@@ -239,7 +241,7 @@ class Sim:
         lib().orc_get_stats(self._h, C.byref(st))
         return dict(newton_calls=st.newton_calls, newton_iters=st.newton_iters,
                     mismatched_links=st.mismatched_links, hist=list(st.hist),
-                    fail_node=st.fail_node, steps=st.steps)
+                    fail_node=st.fail_node, steps=st.steps, fallbacks=st.fallbacks)
 
 
 def rel_err_scalar(a, b):

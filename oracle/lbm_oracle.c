@@ -424,15 +424,40 @@ static void grad_phi(const orc_params* p, int i, double rho, double ux, double u
   *phig = ORC_GRAD_G_COEFF * qc / (rho * Cp);
 }
 
-int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
-                         double T, const double* du, const double* dT, int Lx,
-                         int Ly, int post, double* f, double* g) {
+/* The equilibrium of the constraint set of p at (ux, uy, T) in the lattice's
+ * frame.  Reading (the paper leaves the case open): with p->fallback set,
+ * where the 8-moment problem has no solution (the Newton solve fails, e.g.
+ * a rebuilt link whose source moves at |u'| ~ 1.6 in the receiver's
+ * lattice), the four-constraint equilibrium of the same state stands in,
+ * eq. (feqNum_4Mom): it conserves mass, momentum and energy and exists for
+ * every velocity inside the lattice.  *fell_back (nullable) is set to 1
+ * when it was taken. */
+static int equilibrium_of(const orc_params* p, double ux, double uy, double T, double* w,
+                          double* lam, int* iters, int* fell_back) {
+  int it = 0;
+  int rc = orc_equilibrium_m(constraints_of(p), ux, uy, T, NULL, p->newton_tol,
+                             p->newton_max_iter, w, lam, &it);
+  if (fell_back) *fell_back = 0;
+  if (rc == ORC_ERR_NEWTON && p->fallback && constraints_of(p) == 8) {
+    int it4 = 0;
+    rc = orc_equilibrium_m(4, ux, uy, T, NULL, p->newton_tol, p->newton_max_iter, w, lam,
+                           &it4);
+    it += it4;
+    if (rc == ORC_OK && fell_back) *fell_back = 1;
+  }
+  if (iters) *iters = it;
+  return rc;
+}
+
+static int grad_populations(const orc_params* p, double rho, double ux, double uy,
+                            double T, const double* du, const double* dT, int Lx,
+                            int Ly, int post, double* f, double* g, int* fell_back) {
   double w[ORC_QMAX], lam[ORC_MMAX];
   double Cv = 1.0 / (p->gamma - 1.0);
   const int Q = lattice_of(p);
+  if (fell_back) *fell_back = 0;
   if (!(rho > 0.0) || !isfinite(rho)) return ORC_ERR_NONPHYSICAL;
-  int rc = orc_equilibrium_m(constraints_of(p), ux - Lx, uy - Ly, T, NULL, p->newton_tol,
-                             p->newton_max_iter, w, lam, NULL);
+  int rc = equilibrium_of(p, ux - Lx, uy - Ly, T, w, lam, NULL, fell_back);
   if (rc) return rc;
   double tau = 0.5 + p->nu / T;
   double k = post ? (1.0 - 1.0 / tau) : 1.0;
@@ -471,6 +496,12 @@ int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
     g[i] = geq * (1.0 + k * phig);
   }
   return ORC_OK;
+}
+
+int orc_grad_populations(const orc_params* p, double rho, double ux, double uy,
+                         double T, const double* du, const double* dT, int Lx,
+                         int Ly, int post, double* f, double* g) {
+  return grad_populations(p, rho, ux, uy, T, du, dT, Lx, Ly, post, f, g, NULL);
 }
 
 /* ------------------------------------------------------------ simulation */
@@ -558,7 +589,8 @@ orc_sim* orc_create(const orc_params* p) {
        p->constraints != 13) ||
       p->shift_mode < 0 || p->shift_mode > 3 ||
       (p->shift_mode == 3 && !(p->halfwidth < 1.0)) || !(p->prandtl >= 0.0) ||
-      !(p->prandtl < 1e3))
+      !(p->prandtl < 1e3) || (p->fallback != 0 && p->fallback != 1) ||
+      (p->fallback && (constraints_of(p) != 8 || prandtl_of(p) != 1.0)))
     return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   if (!s) return NULL;
@@ -645,10 +677,10 @@ static int collide_all(orc_sim* s) {
   const double Cv = 1.0 / (p->gamma - 1.0);
   const int Q = s->Q;
   int err = 0;
-  long calls = 0, iters = 0;
+  long calls = 0, iters = 0, fallbacks = 0;
   long hist[ORC_HIST];
   memset(hist, 0, sizeof hist);
-#pragma omp parallel for schedule(static) reduction(+ : calls, iters)
+#pragma omp parallel for schedule(static) reduction(+ : calls, iters, fallbacks)
   for (long n = 0; n < N; ++n) {
     const int Ux = s->Un[2 * n], Uy = s->Un[2 * n + 1];
     double f[ORC_QMAX], g[ORC_QMAX];
@@ -693,11 +725,11 @@ static int collide_all(orc_sim* s) {
     }
     /* numerical equilibrium in the current lattice, eqs. (feqNum_8Mom), (gEq) */
     double w[ORC_QMAX], lam[ORC_MMAX];
-    int it = 0;
-    int rc = orc_equilibrium_m(constraints_of(p), upx, upy, T, NULL, p->newton_tol,
-                               p->newton_max_iter, w, lam, &it);
+    int it = 0, fb = 0;
+    int rc = equilibrium_of(p, upx, upy, T, w, lam, &it, &fb);
     calls += 1;
     iters += it;
+    fallbacks += fb;
     if (rc) {
       record_failure(s, n, rc, &err);
       continue;
@@ -740,6 +772,7 @@ static int collide_all(orc_sim* s) {
   }
   s->st.newton_calls += calls;
   s->st.newton_iters += iters;
+  s->st.fallbacks += fallbacks;
   for (int k = 0; k < ORC_HIST; ++k) s->st.hist[k] += hist[k];
   if (err) return err;
   double* t = s->mac; s->mac = s->mac1; s->mac1 = t;
@@ -769,11 +802,12 @@ static void gradients(const orc_sim* s, const double* v, long n, double du[4],
  * (Sec. IV.A.4): macros and gradients at the source x - c_i, equilibrium in
  * the lattice of the receiving node. */
 static int reconstruct(const orc_sim* s, long src, int Lx, int Ly, int i, double* fi,
-                       double* gi) {
+                       double* gi, int* fell_back) {
   double du[4], dT[2], f[ORC_QMAX], g[ORC_QMAX];
   const double* m = s->mac + 4 * src;
   gradients(s, s->mac, src, du, dT);
-  int rc = orc_grad_populations(&s->p, m[0], m[1], m[2], m[3], du, dT, Lx, Ly, 1, f, g);
+  int rc = grad_populations(&s->p, m[0], m[1], m[2], m[3], du, dT, Lx, Ly, 1, f, g,
+                            fell_back);
   *fi = f[i];
   *gi = g[i];
   return rc;
@@ -798,7 +832,8 @@ int orc_init(orc_sim* s, const double* rho, const double* ux, const double* uy,
   }
   memset(&s->st, 0, sizeof s->st);
   s->st.fail_node = -1;
-#pragma omp parallel for schedule(static)
+  long fallbacks = 0;
+#pragma omp parallel for schedule(static) reduction(+ : fallbacks)
   for (long n = 0; n < N; ++n) {
     int Ux, Uy;
     if (p->shift_mode == 1) {
@@ -818,7 +853,9 @@ int orc_init(orc_sim* s, const double* rho, const double* ux, const double* uy,
     }
     double du[4], dT[2], f[ORC_QMAX], g[ORC_QMAX];
     gradients(s, v, n, du, dT);
-    int rc = orc_grad_populations(p, rho[n], ux[n], uy[n], T[n], du, dT, Ux, Uy, 0, f, g);
+    int fb = 0;
+    int rc = grad_populations(p, rho[n], ux[n], uy[n], T[n], du, dT, Ux, Uy, 0, f, g, &fb);
+    fallbacks += fb;
     if (rc) {
       record_failure(s, n, rc, &err);
       continue;
@@ -831,6 +868,7 @@ int orc_init(orc_sim* s, const double* rho, const double* ux, const double* uy,
     s->Un[2 * n + 1] = Uy;
   }
   free(v);
+  s->st.fallbacks = fallbacks;
   if (err) return err;
   return collide_all(s);
 }
@@ -849,11 +887,11 @@ int orc_step(orc_sim* s, int nsteps) {
   const int Q = s->Q;
   for (int k = 0; k < nsteps; ++k) {
     int err = 0;
-    long mism = 0;
+    long mism = 0, fallbacks = 0;
     /* streaming, eq. (stream), pull form: h_i(x, t+1) = h*_i(x - c_i, t) when
      * x and x - c_i use the same lattice, otherwise eq. (GradGeneral) with
      * macros and gradients at x - c_i (Sec. IV.A.4). */
-#pragma omp parallel for schedule(static) reduction(+ : mism)
+#pragma omp parallel for schedule(static) reduction(+ : mism, fallbacks)
     for (long n = 0; n < N; ++n) {
       const long x = n % nx, y = n / nx;
       const int Ux = s->Un[2 * n], Uy = s->Un[2 * n + 1];
@@ -866,12 +904,15 @@ int orc_step(orc_sim* s, int nsteps) {
           s->gp[i * N + n] = s->g[i * N + src];
         } else {
           mism += 1;
-          int rc = reconstruct(s, src, Ux, Uy, i, &s->fp[i * N + n], &s->gp[i * N + n]);
+          int fb = 0;
+          int rc = reconstruct(s, src, Ux, Uy, i, &s->fp[i * N + n], &s->gp[i * N + n], &fb);
+          fallbacks += fb;
           if (rc) record_failure(s, n, rc, &err);
         }
       }
     }
     s->st.mismatched_links += mism;
+    s->st.fallbacks += fallbacks;
     if (err) return err;
     int rc = collide_all(s);
     if (rc) return rc;

@@ -65,6 +65,11 @@ typedef struct {
   double prandtl;        /* 0 or 1: BGK collision, eq. (coll); otherwise the
                             flexible-Prandtl collision of eq. (Shakhov) with
                             Pr = nu / (thermal diffusivity) */
+  int fallback;          /* 0: a state whose 8-moment equilibrium has no solution
+                            stops the run (ORC_ERR_NEWTON); 1: that collision or
+                            rebuilt link takes the four-constraint equilibrium
+                            of the same state instead (a reading: the paper does
+                            not treat the case); 8 constraints and BGK only */
 } orc_params;
 
 typedef struct {
@@ -74,6 +79,8 @@ typedef struct {
   long hist[ORC_HIST];
   long fail_node;        /* first failing node (lowest index), -1 if none */
   long steps;
+  long fallbacks;        /* collisions and rebuilt links that took the four-
+                            constraint equilibrium (initial condition included) */
 } orc_stats;
 
 typedef struct orc_sim orc_sim;

@@ -51,7 +51,7 @@ def velocities(constraints=8):
 def make_config(nx: int, ny: int, precision="fp64", gamma=1.4, nu=0.0, shift_mode="adaptive",
                 fixed_U=(0, 0), halfwidth=0.5, newton_tol=1e-12, newton_max_iter=30,
                 max_abs_shift=6, sensor=False, stats=False, constraints=8,
-                prandtl=1.0) -> _lib.Config:
+                prandtl=1.0, fallback=False) -> _lib.Config:
     cfg = _lib.Config()
     lib.lbm_default_config(C.byref(cfg), int(nx), int(ny))
     cfg.precision = PRECISIONS[precision]
@@ -67,6 +67,7 @@ def make_config(nx: int, ny: int, precision="fp64", gamma=1.4, nu=0.0, shift_mod
     cfg.collect_stats = int(bool(stats))
     cfg.constraints = int(constraints)
     cfg.prandtl = float(prandtl)
+    cfg.fallback = int(bool(fallback))
     return cfg
 
 
@@ -125,7 +126,8 @@ class Sim:
     def from_workload(cls, wl, precision="fp64", device=None, stream=None, like=None,
                       schedule=None, **over):
         kw = dict(nu=wl.nu, gamma=wl.gamma, shift_mode=wl.shift_mode, fixed_U=wl.fixed_U,
-                  halfwidth=wl.halfwidth, sensor=wl.sensor, precision=precision)
+                  halfwidth=wl.halfwidth, sensor=wl.sensor, precision=precision,
+                  fallback=getattr(wl, "fallback", 0))
         kw.update(over)
         s = cls(wl.nx, wl.ny, device=device, stream=stream, like=like, schedule=schedule, **kw)
         static = wl.static_U if kw["shift_mode"] in (2, "static") else None
@@ -223,7 +225,8 @@ class Sim:
         return dict(steps_done=d.steps_done, status=d.status, fail_step=d.fail_step,
                     fail_node=d.fail_node, newton_calls=d.newton_calls,
                     newton_iters=d.newton_iters, mismatched_links=d.mismatched_links,
-                    iter_hist=list(d.iter_hist), conserved=list(d.conserved))
+                    iter_hist=list(d.iter_hist), conserved=list(d.conserved),
+                    fallback_solves=d.fallback_solves)
 
     def close(self):
         if getattr(self, "_ctx", None) and self._ctx.value:

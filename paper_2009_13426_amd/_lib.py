@@ -20,14 +20,15 @@ class Config(C.Structure):
                 ("shift_halfwidth", C.c_double), ("newton_tol", C.c_double),
                 ("newton_max_iter", C.c_int32), ("max_abs_shift", C.c_int32),
                 ("sensor", C.c_int32), ("collect_stats", C.c_int32), ("constraints", C.c_int32),
-                ("prandtl", C.c_double)]
+                ("prandtl", C.c_double), ("fallback", C.c_int32)]
 
 
 class Diag(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("status", C.c_int32), ("fail_step", C.c_int32),
                 ("fail_node", C.c_int64), ("newton_calls", C.c_int64),
                 ("newton_iters", C.c_int64), ("mismatched_links", C.c_int64),
-                ("iter_hist", C.c_int64 * HIST_BINS), ("conserved", C.c_double * 4)]
+                ("iter_hist", C.c_int64 * HIST_BINS), ("conserved", C.c_double * 4),
+                ("fallback_solves", C.c_int64)]
 
 
 class Schedule(C.Structure):

@@ -46,6 +46,7 @@ struct DevDiag {
   unsigned long long mismatched;
   unsigned long long hist[LBM_HIST_BINS];
   unsigned long long step_base;  // added to the step of a failure (graph replays)
+  unsigned long long fallbacks;  // solves that took the four-constraint equilibrium
 };
 
 enum : unsigned { kCodeNewton = 1, kCodeNonphysical = 2 };
@@ -53,6 +54,7 @@ enum : unsigned { kCodeNewton = 1, kCodeNonphysical = 2 };
 struct Phys {
   double nu, Cv, Cp, halfwidth, tol;
   int max_iter, shift_mode, fixed_ux, fixed_uy, max_abs_shift, sensor, stats;
+  int fallback;   // 1: four-constraint equilibrium where the 8-moment one fails
   double inv_pr;  // 1 / Prandtl number (1: BGK)
 };
 
@@ -392,6 +394,49 @@ __device__ __forceinline__ NewtonOut solve_of(const GuessTable& tb, double ux, d
     return solve_equilibrium(tb, ux, uy, T, P.tol, P.max_iter, w);
 }
 
+// solve_of, and with P.fallback set, where the 8-moment problem has no
+// solution (its solve fails, e.g. a rebuilt link whose source moves at |u'|
+// ~ 1.6 in the receiver's lattice), the four-constraint equilibrium of the
+// same state, eq. (feqNum_4Mom), from the lattice Maxwellian with
+// backtracking: it conserves mass, momentum and energy and exists for every
+// velocity inside the lattice.  The paper leaves the case open; such a
+// solve adds `uses` (the collision, or the rebuilt links it serves) to
+// diag->fallbacks.
+struct FallbackOut {
+  Weights w;
+  NewtonOut no;
+};
+
+// A call, not inlined: the rare path stays out of the register allocation of
+// the kernels' common path.
+__device__ __noinline__ FallbackOut solve_fallback4(double ux, double uy, double T, double tol,
+                                                    int max_iter) {
+  FallbackOut r;
+  double m4[kM4], l4[kM4];
+  targets4(ux, uy, T, m4);
+  r.no = solve_robust4(m4, T, tol, max_iter, r.w, l4);
+  return r;
+}
+
+template <int M>
+__device__ __forceinline__ NewtonOut solve_node(const GuessTable& tb, double ux, double uy,
+                                                double T, const Phys& P, Weights& w,
+                                                DevDiag* diag, unsigned uses = 1u) {
+  NewtonOut no = solve_of<M>(tb, ux, uy, T, P, w);
+  if constexpr (M == kM) {
+    if (!no.ok && P.fallback) {
+      const FallbackOut f = solve_fallback4(ux, uy, T, P.tol, P.max_iter);
+      no.iters += f.no.iters;
+      no.ok = f.no.ok;
+      if (f.no.ok) {
+        w = f.w;
+        atomicAdd(&diag->fallbacks, static_cast<unsigned long long>(uses));
+      }
+    }
+  }
+  return no;
+}
+
 // The rebuilt links of one queued pair: source node s, receiver lattice
 // (Lx, Ly).  Every receiver r = s + c_k + (Lx, Ly) whose next pull is in
 // that lattice and whose link k is marked in its mask gets, in its own slot
@@ -445,7 +490,8 @@ __device__ __forceinline__ void rebuild_pair(const RebuildArgs& a, unsigned long
     return;
   }
   Weights w;
-  const NewtonOut no = solve_of<M>(a.table, ux - Lx, uy - Ly, T, P, w);
+  const NewtonOut no =
+      solve_node<M>(a.table, ux - Lx, uy - Ly, T, P, w, a.diag, static_cast<unsigned>(__popc(take)));
   if (P.stats) {
     atomicAdd(&a.diag->newton_calls, 1ull);
     atomicAdd(&a.diag->newton_iters, static_cast<unsigned long long>(no.iters));
@@ -793,7 +839,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     }
     if (physical) {
       // a5: numerical equilibrium
-      const NewtonOut no = solve_of<M>(a.table, upx, upy, T, P, w);
+      const NewtonOut no = solve_node<M>(a.table, upx, upy, T, P, w, a.diag);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
@@ -1296,7 +1342,7 @@ __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a) {
   a.tout[n] = tag_pack(Ux, Uy, Ux, Uy);
   Weights w;
   if (!code) {
-    const NewtonOut no = solve_of<M>(a.table, ux - Ux, uy - Uy, T, P, w);
+    const NewtonOut no = solve_node<M>(a.table, ux - Ux, uy - Uy, T, P, w, a.diag);
     if (!no.ok) code = kCodeNewton;
   }
   if (code) {

@@ -85,7 +85,8 @@ bool config_ok(const lbm_config* c) {
            c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD)) &&
          c->prandtl >= 0.0 && c->prandtl < 1e3 &&
          (!shakhov_on(c) || (c->prandtl >= 1e-2 && c->constraints != 4 &&
-                             c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD));
+                             c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD)) &&
+         (c->fallback == 0 || (c->fallback == 1 && c->constraints == kM && !shakhov_on(c)));
 }
 
 Layout layout(const lbm_config* c) {
@@ -540,7 +541,7 @@ bool same_config(const lbm_config& a, const lbm_config& b) {
          a.newton_tol == b.newton_tol && a.newton_max_iter == b.newton_max_iter &&
          a.max_abs_shift == b.max_abs_shift && a.sensor == b.sensor &&
          a.collect_stats == b.collect_stats && a.constraints == b.constraints &&
-         a.prandtl == b.prandtl;
+         a.prandtl == b.prandtl && a.fallback == b.fallback;
 }
 
 // Default and checked schedules.
@@ -840,6 +841,7 @@ void lbm_default_config(lbm_config* c, int32_t nx, int32_t ny) {
   c->collect_stats = 0;
   c->constraints = kM;
   c->prandtl = 1.0;
+  c->fallback = 0;
 }
 
 size_t lbm_workspace_bytes(const lbm_config* cfg) {
@@ -889,6 +891,7 @@ lbm_status create_common(const lbm_ctx* like, const lbm_config* cfg, void* ws, s
   c->phys.max_abs_shift = cfg->max_abs_shift;
   c->phys.sensor = cfg->sensor;
   c->phys.stats = cfg->collect_stats;
+  c->phys.fallback = cfg->fallback;
   c->phys.inv_pr = shakhov_on(cfg) ? 1.0 / cfg->prandtl : 1.0;
   c->nblocks = L.nparts;
   c->sched.step_block = cfg->precision == LBM_FP64 ? step_block<double>() : step_block<float>();
@@ -1193,6 +1196,7 @@ lbm_status lbm_get_diag(lbm_ctx* c, lbm_diag* out) {
   out->mismatched_links = static_cast<int64_t>(d.mismatched);
   for (int i = 0; i < LBM_HIST_BINS; ++i) out->iter_hist[i] = static_cast<int64_t>(d.hist[i]);
   for (int i = 0; i < 4; ++i) out->conserved[i] = sums[i];
+  out->fallback_solves = static_cast<int64_t>(d.fallbacks);
   return LBM_OK;
 }
 

@@ -50,6 +50,7 @@ class Workload:
     gamma: float = GAMMA
     sensor: int = 0              # 1: Knudsen-number sensor on the relaxation time
     static_U: Tuple = None       # (Ux, Uy) int arrays for shift_mode 2
+    fallback: int = 0            # 1: four-constraint equilibrium where the 8-moment one fails
     meta: Dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -298,6 +299,12 @@ SERVING_MAX_LINK_SPEED = 1.5
 # lattices differ by two next to each other, and the links rebuilt between
 # them leave the equilibrium's envelope at any viscosity of the ladder.
 SERVING_HALFWIDTH = {"vortex": 0.5, "quadrant": 0.9}
+# Where a state's 8-moment equilibrium has no solution (about 1.8 % of the
+# quadrant draws meet one mid-run: rebuilt links whose source moves at |u'|
+# 1.3-1.9 in the receiver's lattice, or a node's own state behind a strong
+# shock), the serving jobs take the four-constraint equilibrium of that
+# state for that solve instead of stopping (lbm_config.fallback).
+SERVING_FALLBACK = 1
 
 
 @dataclasses.dataclass
@@ -316,11 +323,13 @@ class JobSpec:
             wl = isentropic_vortex(self.side, mach=self.mach, steps=self.steps,
                                    seed_index=4, name=f"job{self.job_id}_vortex", nu=nu)
             wl.halfwidth = SERVING_HALFWIDTH["vortex"]
+            wl.fallback = SERVING_FALLBACK
             return wl
         wl = four_quadrant(self.side, self.steps, seed_index=4,
                            sub=self.job_id + 1, mach=self.mach, nu=nu,
                            max_link_speed=SERVING_MAX_LINK_SPEED)
         wl.halfwidth = SERVING_HALFWIDTH["quadrant"]
+        wl.fallback = SERVING_FALLBACK
         return wl
 
     @property
