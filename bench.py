@@ -179,8 +179,11 @@ def copy_bandwidth(torch, lbm, mib=2048, reps=5):
 
 
 def host_cpu():
-    """Model, sockets and physical cores of the host (from /proc/cpuinfo)."""
+    """Model, sockets and physical cores of the host (from /proc/cpuinfo).
+    Where the model name is generic (virtual machines report "AMD EPYC"),
+    the CPUID family, model and stepping identify the part."""
     model, phys = "", set()
+    ident = {}
     cur = {}
     try:
         with open("/proc/cpuinfo") as f:
@@ -194,12 +197,17 @@ def host_cpu():
                 cur[k] = v
                 if k == "model name" and not model:
                     model = v
+                if k in ("cpu family", "model", "stepping") and k not in ident:
+                    ident[k] = v
         if cur:
             phys.add((cur.get("physical id"), cur.get("core id")))
     except OSError:
         pass
     sockets = len({p for p, _ in phys if p is not None}) or None
     cores = len(phys) if phys and None not in {c for _, c in phys} else None
+    if ident:
+        model = (f"{model} (family {ident.get('cpu family', '?')}, model "
+                 f"{ident.get('model', '?')}, stepping {ident.get('stepping', '?')})")
     return dict(model=model, sockets=sockets, physical_cores=cores,
                 logical_cpus=os.cpu_count(), affinity_cpus=len(os.sched_getaffinity(0)))
 

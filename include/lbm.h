@@ -116,7 +116,8 @@ typedef struct {
                                 backtracking (the paper leaves the case open; it
                                 arises at rebuilt links whose source moves at |u'| ~
                                 1.6 in the receiver's lattice).  Counted in
-                                lbm_diag.fallback_solves.  8 constraints and BGK only */
+                                lbm_diag.fallback_solves.  BGK only (prandtl 1);
+                                without effect for 4 or 13 constraints */
 } lbm_config;
 
 typedef struct {

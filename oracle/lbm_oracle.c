@@ -590,7 +590,7 @@ orc_sim* orc_create(const orc_params* p) {
       p->shift_mode < 0 || p->shift_mode > 3 ||
       (p->shift_mode == 3 && !(p->halfwidth < 1.0)) || !(p->prandtl >= 0.0) ||
       !(p->prandtl < 1e3) || (p->fallback != 0 && p->fallback != 1) ||
-      (p->fallback && (constraints_of(p) != 8 || prandtl_of(p) != 1.0)))
+      (p->fallback && prandtl_of(p) != 1.0))
     return NULL;
   orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
   if (!s) return NULL;

@@ -69,7 +69,8 @@ typedef struct {
                             stops the run (ORC_ERR_NEWTON); 1: that collision or
                             rebuilt link takes the four-constraint equilibrium
                             of the same state instead (a reading: the paper does
-                            not treat the case); 8 constraints and BGK only */
+                            not treat the case); BGK only; without effect for
+                            4 or 13 constraints */
 } orc_params;
 
 typedef struct {

@@ -86,7 +86,7 @@ bool config_ok(const lbm_config* c) {
          c->prandtl >= 0.0 && c->prandtl < 1e3 &&
          (!shakhov_on(c) || (c->prandtl >= 1e-2 && c->constraints != 4 &&
                              c->shift_mode != LBM_SHIFT_NEIGHBOURHOOD)) &&
-         (c->fallback == 0 || (c->fallback == 1 && c->constraints == kM && !shakhov_on(c)));
+         (c->fallback == 0 || (c->fallback == 1 && !shakhov_on(c)));
 }
 
 Layout layout(const lbm_config* c) {

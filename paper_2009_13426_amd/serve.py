@@ -215,6 +215,9 @@ class GpuEngine:
         self.batch_schedule = None
         self.graph = graph          # quanta as replays of a HIP graph (lbm_step_batched_graph)
         self.graph_builds = self.graph_replays = 0
+        # jobs that took the fallback equilibrium (lbm_config.fallback), and
+        # the collisions and rebuilt links that did, over released jobs
+        self.fallback_jobs = self.fallback_solves = 0
 
     def prepare(self, requests: Sequence[Request]):
         """Tunes (or reads from the cache) every schedule the requests need."""
@@ -271,6 +274,10 @@ class GpuEngine:
         return int(self.lib.lbm_step(sim.handle, int(steps)))
 
     def release(self, sim):
+        if sim.cfg.fallback:
+            k = sim.diag()["fallback_solves"]
+            self.fallback_jobs += int(k > 0)
+            self.fallback_solves += k
         sim.close()
         sim.workspace = None
 
@@ -403,6 +410,8 @@ def main(argv=None):
     ap.add_argument("--quantum", type=int, default=50)
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--budget-frac", type=float, default=0.6)
+    ap.add_argument("--graph", action="store_true",
+                    help="quanta as replays of a HIP graph (lbm_step_batched_graph)")
     ap.add_argument("--out", default="")
     args = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -413,7 +422,7 @@ def main(argv=None):
     from . import autotune
     torch.cuda.set_device(0)
     specs = W.serving_jobs(args.jobs)
-    eng = GpuEngine(precision=args.precision)
+    eng = GpuEngine(precision=args.precision, graph=args.graph)
     eng.batch_schedule = autotune.batched_schedule_for(args.precision, device=eng.device)
     free, _ = torch.cuda.mem_get_info()
     budget = int(args.budget_frac * free)
@@ -435,6 +444,7 @@ def main(argv=None):
     rate = args.load * cap["jobs_per_s"]
     print(f"[serve] capacity {cap['jobs_per_s']:.2f} jobs/s on {len(cap_specs)} jobs; "
           f"arrivals at {rate:.2f} jobs/s", flush=True)
+    eng.fallback_jobs = eng.fallback_solves = 0
     rep = serve(requests_prefetched(specs, rate), eng, budget, args.quantum,
                 on_finish=progress("trace", len(specs)))
     summ = rep.summary()
@@ -444,7 +454,9 @@ def main(argv=None):
                load=args.load, rate_jobs_per_s=rate, quantum=args.quantum,
                precision=args.precision, memory_budget_bytes=budget,
                batched_schedule=eng.batch_schedule, summary=summ, failed_jobs=failed,
-               wall_s=time.time() - t0)
+               fallback_jobs=eng.fallback_jobs, fallback_solves=eng.fallback_solves,
+               graph=args.graph, graph_builds=eng.graph_builds,
+               graph_replays=eng.graph_replays, wall_s=time.time() - t0)
     line = json.dumps(out)
     print(line, flush=True)
     if args.out:
