@@ -407,10 +407,46 @@ struct GuessTable {
   float umax, smin, smax, inv_hu, inv_hs;
 };
 
-// lambda guess at (ux, uy, T); returns false (and leaves the lattice
-// Maxwellian in l) when the state is outside the table.
-__device__ __forceinline__ bool table_guess(const GuessTable& tb, double ux, double uy, double iT,
-                                            double (&l)[kM]) {
+// The table's part of a guess at (ux, uy, 1/T): the eight corners of the
+// cell around (|u_x|, |u_y|, 1/T), clamped so that every read stays inside
+// the table, and the interpolation weights.  Split from the interpolation
+// so that a caller can issue the sixteen loads early and use them later.
+struct GuessFetch {
+  float4 v[8][2];
+  float ta, tb, ts;
+  bool inside;
+};
+
+__device__ __forceinline__ GuessFetch table_fetch(const GuessTable& tb, double ux, double uy,
+                                                  double iT) {
+  GuessFetch g;
+  const float a = fabsf(static_cast<float>(ux)), b = fabsf(static_cast<float>(uy));
+  const float s = static_cast<float>(iT);
+  g.inside = a <= tb.umax && b <= tb.umax && s >= tb.smin && s <= tb.smax;
+  const float fa = fminf(a, tb.umax) * tb.inv_hu, fb = fminf(b, tb.umax) * tb.inv_hu;
+  const float fs = (fminf(fmaxf(s, tb.smin), tb.smax) - tb.smin) * tb.inv_hs;
+  const int ia = min(static_cast<int>(fa), tb.nu - 2);
+  const int ib = min(static_cast<int>(fb), tb.nu - 2);
+  const int is = min(static_cast<int>(fs), tb.ns - 2);
+  g.ta = fa - ia;
+  g.tb = fb - ib;
+  g.ts = fs - is;
+  // all sixteen loads in flight before the first is used
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int da = c & 1, db = (c >> 1) & 1, ds = c >> 2;
+    const float4* p = reinterpret_cast<const float4*>(
+        tb.data + (((static_cast<long>(is + ds) * tb.nu + (ib + db)) * tb.nu + (ia + da)) << 3));
+    g.v[c][0] = p[0];
+    g.v[c][1] = p[1];
+  }
+  return g;
+}
+
+// lambda guess at (ux, uy, T) from a fetched cell; returns false (and
+// leaves the lattice Maxwellian in l) when the state is outside the table.
+__device__ __forceinline__ bool table_guess_from(const GuessFetch& g, double ux, double uy,
+                                                 double iT, double (&l)[kM]) {
   l[0] = 0.0;
   l[1] = -ux * iT;
   l[2] = -uy * iT;
@@ -419,42 +455,22 @@ __device__ __forceinline__ bool table_guess(const GuessTable& tb, double ux, dou
   l[5] = 0.5 * iT;
   l[6] = 0.0;
   l[7] = 0.0;
-  const float a = fabsf(static_cast<float>(ux)), b = fabsf(static_cast<float>(uy));
-  const float s = static_cast<float>(iT);
-  const bool inside = a <= tb.umax && b <= tb.umax && s >= tb.smin && s <= tb.smax;
-  // clamped cell index: every corner read stays inside the table
-  const float fa = fminf(a, tb.umax) * tb.inv_hu, fb = fminf(b, tb.umax) * tb.inv_hu;
-  const float fs = (fminf(fmaxf(s, tb.smin), tb.smax) - tb.smin) * tb.inv_hs;
-  const int ia = min(static_cast<int>(fa), tb.nu - 2);
-  const int ib = min(static_cast<int>(fb), tb.nu - 2);
-  const int is = min(static_cast<int>(fs), tb.ns - 2);
-  const float ta = fa - ia, tb_ = fb - ib, ts = fs - is;
-  // all sixteen loads in flight before the first is used
-  float4 v[8][2];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int da = c & 1, db = (c >> 1) & 1, ds = c >> 2;
-    const float4* p = reinterpret_cast<const float4*>(
-        tb.data + (((static_cast<long>(is + ds) * tb.nu + (ib + db)) * tb.nu + (ia + da)) << 3));
-    v[c][0] = p[0];
-    v[c][1] = p[1];
-  }
   float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const int da = c & 1, db = (c >> 1) & 1, ds = c >> 2;
-    const float wgt = (da ? ta : 1.0f - ta) * (db ? tb_ : 1.0f - tb_) * (ds ? ts : 1.0f - ts);
-    acc[0] = __builtin_fmaf(wgt, v[c][0].x, acc[0]);
-    acc[1] = __builtin_fmaf(wgt, v[c][0].y, acc[1]);
-    acc[2] = __builtin_fmaf(wgt, v[c][0].z, acc[2]);
-    acc[3] = __builtin_fmaf(wgt, v[c][0].w, acc[3]);
-    acc[4] = __builtin_fmaf(wgt, v[c][1].x, acc[4]);
-    acc[5] = __builtin_fmaf(wgt, v[c][1].y, acc[5]);
-    acc[6] = __builtin_fmaf(wgt, v[c][1].z, acc[6]);
-    acc[7] = __builtin_fmaf(wgt, v[c][1].w, acc[7]);
+    const float wgt = (da ? g.ta : 1.0f - g.ta) * (db ? g.tb : 1.0f - g.tb) * (ds ? g.ts : 1.0f - g.ts);
+    acc[0] = __builtin_fmaf(wgt, g.v[c][0].x, acc[0]);
+    acc[1] = __builtin_fmaf(wgt, g.v[c][0].y, acc[1]);
+    acc[2] = __builtin_fmaf(wgt, g.v[c][0].z, acc[2]);
+    acc[3] = __builtin_fmaf(wgt, g.v[c][0].w, acc[3]);
+    acc[4] = __builtin_fmaf(wgt, g.v[c][1].x, acc[4]);
+    acc[5] = __builtin_fmaf(wgt, g.v[c][1].y, acc[5]);
+    acc[6] = __builtin_fmaf(wgt, g.v[c][1].z, acc[6]);
+    acc[7] = __builtin_fmaf(wgt, g.v[c][1].w, acc[7]);
   }
   // outside the table, or a corner that failed to converge: Maxwellian start
-  const bool ok = inside && fabsf(acc[7]) < 1e30f;
+  const bool ok = g.inside && fabsf(acc[7]) < 1e30f;
   const double sx = ux < 0.0 ? -1.0 : 1.0, sy = uy < 0.0 ? -1.0 : 1.0;
 #pragma unroll
   for (int k = 0; k < 7; ++k) acc[k] = ok ? acc[k] : 0.0f;
@@ -467,6 +483,11 @@ __device__ __forceinline__ bool table_guess(const GuessTable& tb, double ux, dou
   l[6] += sx * acc[5];
   l[7] += sy * acc[6];
   return ok;
+}
+
+__device__ __forceinline__ bool table_guess(const GuessTable& tb, double ux, double uy, double iT,
+                                            double (&l)[kM]) {
+  return table_guess_from(table_fetch(tb, ux, uy, iT), ux, uy, iT, l);
 }
 
 // H accumulated directly from the weights, one +- pair at a time: the pair
@@ -628,15 +649,17 @@ __device__ __forceinline__ void constraint_moments(const Weights& w, double (&c)
 // final correction, solved with the factors of the last step, which are
 // kept in registers: the residual is at the tolerance, so factors of a
 // Hessian that moved by the size of that step take it to round-off.
-__device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux, double uy,
-                                                double T, double tol, int max_iter, Weights& w) {
+// g: the table cell of (ux, uy, iT = 1/T), fetched by the caller.
+__device__ __forceinline__ NewtonOut solve_fast(const GuessFetch& g, double iT, double ux,
+                                                double uy, double T, double tol, int max_iter,
+                                                Weights& w) {
   NewtonOut out{0, false};
   {
     // The first weights must be of exponential form to full FP64 accuracy:
     // the multiplicative updates below never touch components outside the
     // span of phi, so any noise introduced here would survive to the end.
     double l[kM];
-    table_guess(tb, ux, uy, rcp64(T), l);
+    table_guess_from(g, ux, uy, iT, l);
     l[0] = -1.0;
     eval_weights(l, w);
   }
@@ -706,6 +729,29 @@ __device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux,
       for (int a = 0; a < kM; ++a) G[a] *= sc;
     }
     exp_update(G, w);
+  }
+  return out;
+}
+
+// solve_fast with its own fetch of the table cell.
+__device__ __forceinline__ NewtonOut solve_fast(const GuessTable& tb, double ux, double uy,
+                                                double T, double tol, int max_iter, Weights& w) {
+  const double iT = rcp64(T);
+  return solve_fast(table_fetch(tb, ux, uy, iT), iT, ux, uy, T, tol, max_iter, w);
+}
+
+// solve_fast from a cell fetched by the caller (table_fetch at iT = 1/T),
+// and where it fails (a state far from the table or a start from which plain
+// Newton steps do not converge) the globalised solve_robust.
+__device__ __forceinline__ NewtonOut solve_equilibrium(const GuessFetch& g, double iT, double ux,
+                                                       double uy, double T, double tol,
+                                                       int max_iter, Weights& w) {
+  NewtonOut out = solve_fast(g, iT, ux, uy, T, tol, max_iter, w);
+  if (!out.ok) {
+    double l[kM];
+    const NewtonOut r = solve_robust(ux, uy, T, tol, max_iter, w, l);
+    out.iters += r.iters;
+    out.ok = r.ok;
   }
   return out;
 }

@@ -418,22 +418,38 @@ __device__ __noinline__ FallbackOut solve_fallback4(double ux, double uy, double
   return r;
 }
 
+// With P.fallback set, a failed 8-moment solve (no) is replaced by the
+// four-constraint one of the same state.
+__device__ __forceinline__ void fallback_if_failed(NewtonOut& no, double ux, double uy, double T,
+                                                   const Phys& P, Weights& w, DevDiag* diag,
+                                                   unsigned uses) {
+  if (!no.ok && P.fallback) {
+    const FallbackOut f = solve_fallback4(ux, uy, T, P.tol, P.max_iter);
+    no.iters += f.no.iters;
+    no.ok = f.no.ok;
+    if (f.no.ok) {
+      w = f.w;
+      atomicAdd(&diag->fallbacks, static_cast<unsigned long long>(uses));
+    }
+  }
+}
+
 template <int M>
 __device__ __forceinline__ NewtonOut solve_node(const GuessTable& tb, double ux, double uy,
                                                 double T, const Phys& P, Weights& w,
                                                 DevDiag* diag, unsigned uses = 1u) {
   NewtonOut no = solve_of<M>(tb, ux, uy, T, P, w);
-  if constexpr (M == kM) {
-    if (!no.ok && P.fallback) {
-      const FallbackOut f = solve_fallback4(ux, uy, T, P.tol, P.max_iter);
-      no.iters += f.no.iters;
-      no.ok = f.no.ok;
-      if (f.no.ok) {
-        w = f.w;
-        atomicAdd(&diag->fallbacks, static_cast<unsigned long long>(uses));
-      }
-    }
-  }
+  if constexpr (M == kM) fallback_if_failed(no, ux, uy, T, P, w, diag, uses);
+  return no;
+}
+
+// The same for the 8-moment set from a table cell the caller fetched
+// (table_fetch at iT = 1/T) ahead of the solve.
+__device__ __forceinline__ NewtonOut solve_node(const GuessFetch& g, double iT, double ux,
+                                                double uy, double T, const Phys& P, Weights& w,
+                                                DevDiag* diag) {
+  NewtonOut no = solve_equilibrium(g, iT, ux, uy, T, P.tol, P.max_iter, w);
+  fallback_if_failed(no, ux, uy, T, P, w, diag, 1u);
   return no;
 }
 
@@ -599,6 +615,20 @@ __device__ __forceinline__ double sensor_alpha(double eps) {
 // Wrapped source columns and row offsets of node (x, y) for a pull in
 // lattice (ux, uy): link k's source is (x - cx - ux, y - cy - uy) and the
 // offsets cx + ux, cy + uy take seven values each (cx, cy in [-3, 3]).
+// Lattice tags read through a buffer resource: one descriptor and a 32-bit
+// byte offset per load (plain loads of the tag array took a 64-bit address
+// per lane and load).  Offsets stay below the n tags the descriptor covers.
+struct TagReader {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ TagReader(const int* tags, long long n)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<int*>(tags), static_cast<short>(0),
+                                            static_cast<int>(n * 4), 0x00020000)) {}
+  __device__ __forceinline__ int operator()(unsigned idx) const {
+    return static_cast<int>(
+        __builtin_amdgcn_raw_buffer_load_b32(r, static_cast<int>(idx * 4u), 0, 0));
+  }
+};
+
 struct PullMap {
   int col[7], row[7];
   __device__ __forceinline__ void build(int x, int y, int ux, int uy, const Grid& g) {
@@ -734,6 +764,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   double rho = 0.0, jx = 0.0, jy = 0.0, e = 0.0;
   PullMap pm;  // sources of this pull; the next pull reuses them unless the lattice changes
   int st[kQ];  // tags of the next pull's sources, loaded with this pull's populations
+  const TagReader tag_at(a.tin, N);
   if (active) {
     S fv[kQ], gv[kQ];
     if constexpr (STREAM) {
@@ -747,7 +778,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
       if (P.shift_mode != 1) {
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          st[k] = plane_at(a.tin, pm.template source<k>());
+          st[k] = tag_at(pm.template source<k>());
         });
       }
       // rebuilt links (rare: a wave-uniform test skips this for most waves)
@@ -797,6 +828,16 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     int iters = 0;
     const bool physical = rho > 0.0 && T > 0.0 && rho < 1e300 && T < 1e300 &&
                           fabs(upx) < 1e300 && fabs(upy) < 1e300;
+    // the guess table's cell, loaded now so that its latency is spent on
+    // the lattice choice and the next-pull mask below (8-moment set)
+    GuessFetch gf;
+    double iT = 0.0;
+    if constexpr (M == kM) {
+      if (physical) {
+        iT = rcp64(T);
+        gf = table_fetch(a.table, upx, upy, iT);
+      }
+    }
     if (!physical) {
       code = kCodeNonphysical;
     } else if (NBH ? P.shift_mode == 3 : P.shift_mode == 0) {
@@ -828,7 +869,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
         pm.build(x, y, nux, nuy, a.grid);
         static_for<0, kQ>([&](auto kc) {
           constexpr int k = decltype(kc)::value;
-          st[k] = plane_at(a.tin, pm.template source<k>());
+          st[k] = tag_at(pm.template source<k>());
         });
       }
       const int nun16 = (nux & 0xFF) | ((nuy & 0xFF) << 8);
@@ -839,7 +880,11 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     }
     if (physical) {
       // a5: numerical equilibrium
-      const NewtonOut no = solve_node<M>(a.table, upx, upy, T, P, w, a.diag);
+      NewtonOut no;
+      if constexpr (M == kM)
+        no = solve_node(gf, iT, upx, upy, T, P, w, a.diag);
+      else
+        no = solve_node<M>(a.table, upx, upy, T, P, w, a.diag);
       iters = no.iters;
       if (!no.ok && !code) code = kCodeNewton;
     }
