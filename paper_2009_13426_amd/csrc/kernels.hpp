@@ -735,6 +735,8 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
   const long long n = static_cast<long long>(b) * BLOCK + tid;
   const bool active = n < N;
   const Phys& P = a.phys;
+  // the wave issues its loads ahead of the SIMD's other wave, then yields
+  __builtin_amdgcn_s_setprio(2);
   const S* fin = static_cast<const S*>(a.fin);
   const S* gin = static_cast<const S*>(a.gin);
   S* fout = static_cast<S*>(a.fout);
@@ -781,6 +783,7 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
           st[k] = tag_at(pm.template source<k>());
         });
       }
+      __builtin_amdgcn_s_setprio(0);
       // rebuilt links (rare: a wave-uniform test skips this for most waves)
       if (__ballot(mism != 0u)) {
         static_for<0, kQ>([&](auto kc) {
@@ -835,7 +838,9 @@ __device__ __forceinline__ void step_body(const StepArgs& a, int b) {
     if constexpr (M == kM) {
       if (physical) {
         iT = rcp64(T);
+        __builtin_amdgcn_s_setprio(2);
         gf = table_fetch(a.table, upx, upy, iT);
+        __builtin_amdgcn_s_setprio(0);
       }
     }
     if (!physical) {
