@@ -5,11 +5,12 @@ differences (shocks and the sensor at low viscosity), the floor for any two
 FP64 implementations that round differently; computed with the CPU oracle
 only.  Run from the repository root:
 
-    python tests/golden/make_sensitivity.py
+    python tests/golden/make_sensitivity.py [case ...]
 
-Cases: the advected Sod tube (2048 x 4, 2000 steps, workloads.config1) and
+Cases: the advected Sod tube (2048 x 4, 2000 steps, workloads.config1),
 the quarter-size copy of the isentropic vortex (256^2, 1250 steps,
-workloads.config2(256, 1250)).  Per checkpoint: max and median over nodes
+workloads.config2(256, 1250)) and the 512^2 copy of the four-quadrant draw
+(125 steps, workloads.config3(512, 125)).  Per checkpoint: max and median over nodes
 of the relative error of rho, T and u (u relative to the largest |u|),
 between the run from the drawn fields and the run whose initial density is
 moved up by one ulp at every node.
@@ -31,6 +32,7 @@ CASES = {
     "advected_sod_2048x4": (lambda: W.config1(2048, 4, 2000),
                             [150, 300, 500, 750, 1000, 1500, 2000]),
     "vortex_256": (lambda: W.config2(256, 1250), [100, 250, 500, 750, 1000, 1250]),
+    "quadrant_512": (lambda: W.config3(512, 125), [25, 50, 75, 100, 125]),
 }
 
 
@@ -61,8 +63,16 @@ def run(name):
 
 
 if __name__ == "__main__":
-    res = {name: run(name) for name in CASES}
+    # python tests/golden/make_sensitivity.py [case ...]: all cases, or the
+    # named ones merged into the existing file
+    path = os.path.join(HERE, "sensitivity.json")
+    names = sys.argv[1:] or list(CASES)
+    res = {}
+    if sys.argv[1:] and os.path.exists(path):
+        with open(path) as f:
+            res = json.load(f)
+    res.update({name: run(name) for name in names})
     res["_doc"] = ("oracle against itself with the initial density moved up by one ulp: "
                    "max and median over nodes of the relative error of rho, T and u")
-    with open(os.path.join(HERE, "sensitivity.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(res, f, indent=1)

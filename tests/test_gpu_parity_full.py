@@ -266,6 +266,43 @@ def test_vortex_256_full_horizon(lbm, precision):
         compare(got, ref, "fp32", f"vortex_256/fp32/{steps}", fp32_bound=VORTEX_FP32_BOUND)
 
 
+# FP32 storage on the four-quadrant copy after its 125 steps: the 1e-5
+# bound of the form (measured 4.5e-7, median 7.9e-8)
+QUADRANT_FP32_BOUND = 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_quadrant_512_full_horizon(lbm, precision):
+    """The four-quadrant draw's 512^2 copy over 125 steps (the fraction of
+    the domain its waves cross in 1000 steps at 4096^2; shocks, lattice
+    changes, rebuilt links and the sensor throughout) on the GPU, against
+    sampled rows of the oracle's run stored by
+    tests/golden/make_quadrant_golden.py.  FP64: within 1e-12, or four
+    times the oracle's own one-ulp drift at this horizon where that is
+    larger.  FP32 storage: within 1e-5."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "quadrant_512_125.npz"),
+                allow_pickle=False)
+    L, steps, rows = int(g["L"]), int(g["steps"]), g["rows"]
+    wl = W.config3(L, steps)
+    sim = lbm.Sim.from_workload(wl, precision=precision)
+    sim.step(steps)
+    m = sim.macros()
+    got = {k: m[k].cpu().numpy()[rows].ravel() for k in ("rho", "ux", "uy", "T")}
+    tags = (m["Ux"].cpu().numpy()[rows].ravel(), m["Uy"].cpu().numpy()[rows].ravel())
+    sim.close()
+    ref = {k: g[k].ravel() for k in ("rho", "ux", "uy", "T")}
+    if precision == "fp64":
+        mx, med = _sensitivity("quadrant_512", steps)
+        print(f"oracle one-ulp drift at {steps}: max {mx:.2e} median {med:.2e}", flush=True)
+        compare(got, ref, "fp64", f"quadrant_512/fp64/{steps}",
+                fp64_bounds=(max(1e-12, 4 * mx), max(1e-12, 4 * med)))
+        assert np.array_equal(tags[0], g["Ucx"].ravel()) and \
+            np.array_equal(tags[1], g["Ucy"].ravel())
+    else:
+        compare(got, ref, "fp32", f"quadrant_512/fp32/{steps}", fp32_bound=QUADRANT_FP32_BOUND)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_bench_launch_configuration_is_bitwise_the_plain_one(lbm, precision, tmp_path,
                                                            monkeypatch):
