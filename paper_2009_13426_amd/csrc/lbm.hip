@@ -744,7 +744,11 @@ lbm_status step_batched_common(lbm_ctx* const* ctxs, const int32_t* nsteps, int3
   HIP_TRY(hipMemcpyAsync(dev_jobs, host_jobs, n * sizeof(JobArgs), hipMemcpyHostToDevice,
                          c0->stream));
   const dim3 step_grid(static_cast<unsigned>(blocks));
-  const dim3 rebuild_grid(static_cast<unsigned>(std::min<long long>((nodes + kBlock - 1) / kBlock, 4096)));
+  // queue and rebuild: each workgroup first sums the jobs' counts, so the
+  // grid follows the batch's size (one 256-lane workgroup per 2048 nodes)
+  // between two and four workgroups per CU
+  const dim3 rebuild_grid(
+      static_cast<unsigned>(std::clamp<long long>((nodes + 2047) / 2048, 512, 1024)));
   const void* rebuild_batched = rebuild_batched_fn(c0->cfg.precision, c0->cfg.constraints);
   int remap = c0->sched.xcd_remap;
   if (graph && most > 0) {
