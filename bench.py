@@ -33,7 +33,8 @@ a copy), reported only while the committed profile summary was taken on
 the current kernel sources.  The kernel spends most of its time in FP64
 Newton arithmetic, so `roofline.alu` gives beside it the FP64 flops and
 VALU instructions per node (from the same summary), the achieved FP64 rate
-against the 78.6 TFLOP/s vector peak and the VALU issue fraction.
+against the 78.6 TFLOP/s vector peak and the VALU issue fraction, at
+2.4 GHz and at the engine clock the summary measured during that kernel.
 """
 import argparse
 import json
@@ -380,6 +381,9 @@ def main():
     t_step = res[head]["kernel_ms"] * 1e-3
     flops = float(prof.get(f"{head}.fp64_flops_per_node", "nan"))
     valu = float(prof.get(f"{head}.valu_insts_per_node", "nan"))
+    # the engine clock the profile measured during this kernel (GRBM_GUI_ACTIVE
+    # per XCC over the dispatch time): the VALU issue limit at that clock
+    clk = float(prof[f"{head}.engine_clock_ghz"]) if f"{head}.engine_clock_ghz" in prof else None
     traffic = None
     if fresh:
         traffic = round(float(prof[f"{head}.fetch_bytes_per_launch"]) +
@@ -398,7 +402,11 @@ def main():
                              peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                              frac=round(ach / FP64_PEAK_TFLOPS, 4),
                              valu_insts_per_node=valu,
-                             valu_issue_frac=round(valu * nodes / t_step / VALU_ISSUE_PEAK, 4)))
+                             valu_issue_frac=round(valu * nodes / t_step / VALU_ISSUE_PEAK, 4),
+                             engine_clock_ghz=clk,
+                             valu_issue_frac_at_clock=round(
+                                 valu * nodes / t_step / (VALU_ISSUE_PEAK * clk / 2.4), 4)
+                             if clk else None))
     serving = None
     if not args.no_serve:
         print("[bench] serving mix", file=sys.stderr, flush=True)
