@@ -100,6 +100,25 @@ def test_quadrant_4096_sampled(lbm, orc, precision):
     compare(got, ref, precision, f"quadrant_4096/{precision}")
 
 
+_LONGER_REF = {}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_quadrant_4096_sampled_32_steps(lbm, orc, precision):
+    """The same draw further on: 32 steps, by which the waves from the
+    quadrant lines have crossed about 80 nodes and rebuilt links sit at the
+    lattice interfaces they carry; six sampled nodes (the oracle's crops,
+    529 x 529, are shared by both forms)."""
+    steps = 32
+    wl = W.four_quadrant(4096, steps)
+    pts = sample_centres(wl, 6, seed=17)
+    print(f"quadrant 4096^2 {precision}, {steps} steps, {len(pts)} sampled nodes", flush=True)
+    got = gpu_values(lbm, wl, steps, precision, pts)
+    if "ref" not in _LONGER_REF:
+        _LONGER_REF["ref"] = oracle_values(orc, wl, steps, pts)
+    compare(got, _LONGER_REF["ref"], precision, f"quadrant_4096_32/{precision}")
+
+
 # the variants bench.py times on the same draw: (precision, options, steps,
 # sampled nodes); the reference model's crops are few and short (its oracle
 # is about ten times slower per node)
