@@ -1,8 +1,9 @@
 """The oracle against a second, independent implementation of the same model:
-a vectorised numpy D2Q21 DDF-BGK on periodic lines one node tall, written
-here from the paper's definitions and sharing no code with the oracle.
-First on the shear wave in one lattice (Sec. IV.B.1), then with lattices
-that follow the flow, rebuilt links and the sensor (a1-a6 of the step).
+a vectorised numpy D2Q21 DDF-BGK on periodic grids, written here from the
+paper's definitions and sharing no code with the oracle.  First on the
+shear wave in one lattice (Sec. IV.B.1), then with lattices that follow the
+flow, rebuilt links and the sensor (a1-a6 of the step) on lines and on
+small 2D grids.
 
 What differs from the oracle: the populations are held node x velocity and
 streamed with np.roll (in the one-lattice case in the frame of the lattice,
@@ -164,22 +165,22 @@ def sensor_alpha(eps):
     return a
 
 
-def grad_pops(rho, ux, uy, T, dux, duy, dT, Lx, Ly, nu, k):
+def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k):
     """h_eq (1 + k phi_h) of eqs. (GradGeneral_f), (GradGeneral_g) in lattice
-    (Lx, Ly) at absolute (rho, u, T), x-derivatives dux = d_x u_x, duy = d_x
-    u_y, dT = d_x T (the y-derivatives vanish on the line); mu = rho nu,
-    kappa = rho Cp nu (unit Prandtl number)."""
+    (Lx, Ly) at absolute (rho, u, T); du = (d_x u_x, d_y u_x, d_x u_y,
+    d_y u_y), dT = (d_x T, d_y T); mu = rho nu, kappa = rho Cp nu (unit
+    Prandtl number)."""
     Cp = GAMMA * CV
     w = equilibrium_weights(ux - Lx, uy - Ly, T)
     cx = CX[None, :] + Lx[:, None] - ux[:, None]
     cy = CY[None, :] + Ly[:, None] - uy[:, None]
     mu = rho * nu
-    div = dux
-    sxx = -mu * (2.0 * dux - (2.0 / D) * div)
-    syy = -mu * (0.0 - (2.0 / D) * div)
-    sxy = -mu * duy
-    qx = -rho * Cp * nu * dT
-    qc = qx[:, None] * cx
+    div = du[0] + du[3]
+    sxx = -mu * (2.0 * du[0] - (2.0 / D) * div)
+    syy = -mu * (2.0 * du[3] - (2.0 / D) * div)
+    sxy = -mu * (du[1] + du[2])
+    kappa = rho * Cp * nu
+    qc = -kappa[:, None] * (dT[0][:, None] * cx + dT[1][:, None] * cy)
     c2 = cx * cx + cy * cy
     r, t = rho[:, None], T[:, None]
     phif = (sxx[:, None] * cx * cx + 2 * sxy[:, None] * cx * cy + syy[:, None] * cy * cy) \
@@ -191,20 +192,31 @@ def grad_pops(rho, ux, uy, T, dux, duy, dT, Lx, Ly, nu, k):
     return feq * (1 + k * phif), geq * (1 + k * phig)
 
 
-def ddx(a):
-    return 0.5 * (np.roll(a, -1) - np.roll(a, 1))
+def central(a, nx, ny):
+    """Periodic central differences of a field stored row-major (ny rows of
+    nx nodes): (d_x a, d_y a), flattened."""
+    a = a.reshape(ny, nx)
+    return (0.5 * (np.roll(a, -1, 1) - np.roll(a, 1, 1))).ravel(), \
+        (0.5 * (np.roll(a, -1, 0) - np.roll(a, 1, 0))).ravel()
 
 
-class AdaptiveLine:
+def gradients(ux, uy, T, nx, ny):
+    (uxx, uxy), (uyx, uyy), (Tx, Ty) = (central(a, nx, ny) for a in (ux, uy, T))
+    return (uxx, uxy, uyx, uyy), (Tx, Ty)
+
+
+class AdaptiveGrid:
+    """The adaptive model on a periodic nx x ny grid (row-major nodes)."""
+
     def __init__(self, wl):
-        assert wl.ny == 1
         self.nu, self.hw, self.sensor = wl.nu, wl.halfwidth, wl.sensor
+        self.nx, self.ny = wl.nx, wl.ny
         rho, ux, uy, T = (a.ravel().copy() for a in (wl.rho, wl.ux, wl.uy, wl.T))
-        self.nx = rho.size
         Lx = np.ceil(ux - 0.5).astype(int)
         Ly = np.ceil(uy - 0.5).astype(int)
         # Grad initial condition (Sec. IV.A.1, reading: pre-collision), then a collision
-        f, g = grad_pops(rho, ux, uy, T, ddx(ux), ddx(uy), ddx(T), Lx, Ly, self.nu, 1.0)
+        du, dT = gradients(ux, uy, T, self.nx, self.ny)
+        f, g = grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, self.nu, 1.0)
         self.collide(f, g, Lx, Ly)
 
     def select(self, u, L):
@@ -230,20 +242,24 @@ class AdaptiveLine:
 
     def step(self):
         Lx, Ly = self.Un
-        x = np.arange(self.nx)
-        src = (x[:, None] - (CX.astype(int)[None, :] + Lx[:, None])) % self.nx   # node x plane
+        n = np.arange(self.nx * self.ny)
+        x, y = n % self.nx, n // self.nx
+        sx = (x[:, None] - (CX.astype(int)[None, :] + Lx[:, None])) % self.nx
+        sy = (y[:, None] - (CY.astype(int)[None, :] + Ly[:, None])) % self.ny
+        src = sy * self.nx + sx                                   # node x plane
         same = (self.Uc[0][src] == Lx[:, None]) & (self.Uc[1][src] == Ly[:, None])
-        f = np.where(same, self.f[src, np.arange(21)[None, :]], 0.0)
-        g = np.where(same, self.g[src, np.arange(21)[None, :]], 0.0)
-        nodes, planes = np.nonzero(~same)
+        planes = np.arange(21)[None, :]
+        f = np.where(same, self.f[src, planes], 0.0)
+        g = np.where(same, self.g[src, planes], 0.0)
+        nodes, ks = np.nonzero(~same)
         if nodes.size:
-            s = src[nodes, planes]
+            s = src[nodes, ks]
             rho, ux, uy, T = (a[s] for a in self.mac)
-            d = [ddx(a)[s] for a in self.mac[1:]]
-            hf, hg = grad_pops(rho, ux, uy, T, *d, Lx[nodes], Ly[nodes], self.nu,
-                               1.0 - 1.0 / (0.5 + self.nu / T))
-            f[nodes, planes] = hf[np.arange(nodes.size), planes]
-            g[nodes, planes] = hg[np.arange(nodes.size), planes]
+            du, dT = gradients(*self.mac[1:], self.nx, self.ny)
+            hf, hg = grad_pops(rho, ux, uy, T, [d[s] for d in du], [d[s] for d in dT],
+                               Lx[nodes], Ly[nodes], self.nu, 1.0 - 1.0 / (0.5 + self.nu / T))
+            f[nodes, ks] = hf[np.arange(nodes.size), ks]
+            g[nodes, ks] = hg[np.arange(nodes.size), ks]
         self.rebuilt = nodes.size
         return self.collide(f, g, Lx, Ly)
 
@@ -257,16 +273,24 @@ ADAPTIVE_CASES = {
     # plain criterion, no sensor: about 280 rebuilt links a step
     "sod_at_lattice_boundary": lambda steps: W.sod(256, 1, u0=1.45, nu=1e-2, shift_mode=0,
                                                    halfwidth=0.5, sensor=0, steps=steps),
+    # 2D: the four-quadrant draw of the benchmark at 64^2, the Table 1
+    # Riemann problem at 48^2 and the advected vortex at 48^2 (sensor on,
+    # y-gradients, shear stress and heat flux in both directions); 1 000 to
+    # 6 000 rebuilt links a step
+    "four_quadrant_64": lambda steps: W.four_quadrant(64, steps),
+    "riemann_table1_48": lambda steps: W.riemann_table1(48, steps=steps),
+    "vortex_48": lambda steps: W.config2(48, steps),
 }
+ADAPTIVE_STEPS = {"four_quadrant_64": 20, "riemann_table1_48": 20, "vortex_48": 20}
 
 
 @pytest.mark.parametrize("case", list(ADAPTIVE_CASES))
 def test_independent_adaptive_line_matches_the_oracle(case):
-    """After 40 steps the two agree to 1e-10 on every node, select the same
-    lattices and rebuild the same number of links."""
-    steps = 40
+    """After 40 steps (20 on the 2D grids) the two agree to 1e-10 on every
+    node, select the same lattices and rebuild the same number of links."""
+    steps = ADAPTIVE_STEPS.get(case, 40)
     wl = ADAPTIVE_CASES[case](steps)
-    line = AdaptiveLine(wl)
+    line = AdaptiveGrid(wl)
     rebuilt = 0
     for _ in range(steps):
         line.step()
@@ -275,7 +299,7 @@ def test_independent_adaptive_line_matches_the_oracle(case):
     s.step(steps)
     m = {k: v.ravel() for k, v in s.macros().items()}
     rho, ux, uy, T = line.mac
-    uscale = np.abs(m["ux"]).max()
+    uscale = np.hypot(m["ux"], m["uy"]).max()
     err = dict(rho=(np.abs(rho - m["rho"]) / m["rho"]).max(),
                T=(np.abs(T - m["T"]) / m["T"]).max(),
                u=(np.hypot(ux - m["ux"], uy - m["uy"]) / uscale).max())
