@@ -52,22 +52,28 @@ def maxwellian_targets(ux, uy, T):
                      ux * (u2 + (D + 2) * T), uy * (u2 + (D + 2) * T)], 1)
 
 
-def equilibrium_weights(ux, uy, T, tol=1e-12):
+def equilibrium_weights(ux, uy, T, tol=1e-12, constraints=8):
     """w_i = exp(-lambda . phi_i) with sum_i w_i phi_i = targets: Newton from
     the lattice Maxwellian on the convex dual Psi = sum_i w_i + lambda . m,
     each step halved while it raises Psi (one final full step after the
     tolerance)."""
-    m = maxwellian_targets(ux, uy, T)
-    lam = np.zeros((ux.size, 8))
+    if constraints == 8:
+        phi, m = PHI, maxwellian_targets(ux, uy, T)
+        lam = np.zeros((ux.size, 8))
+        lam[:, 3] = lam[:, 5] = 0.5 / T
+    else:  # mass, momentum and energy only (eq. feqNum_4Mom)
+        phi = np.stack([np.ones(21), CX, CY, SQ], 1)
+        m = np.stack([np.ones_like(ux), ux, uy, ux * ux + uy * uy + D * T], 1)
+        lam = np.zeros((ux.size, 4))
+        lam[:, 3] = 0.5 / T
     lam[:, 1], lam[:, 2] = -ux / T, -uy / T
-    lam[:, 3] = lam[:, 5] = 0.5 / T
-    lam[:, 0] = np.log(np.exp(-(lam[:, 1:] @ PHI[:, 1:].T)).sum(1))
-    psi = lambda l: np.exp(-(l @ PHI.T)).sum(1) + (l * m).sum(1)
+    lam[:, 0] = np.log(np.exp(-(lam[:, 1:] @ phi[:, 1:].T)).sum(1))
+    psi = lambda l: np.exp(-(l @ phi.T)).sum(1) + (l * m).sum(1)
     done = np.zeros(ux.size, dtype=bool)
     for _ in range(200):
-        w = np.exp(-(lam @ PHI.T))
-        G = w @ PHI - m
-        H = np.einsum("ni,ia,ib->nab", w, PHI, PHI)
+        w = np.exp(-(lam @ phi.T))
+        G = w @ phi - m
+        H = np.einsum("ni,ia,ib->nab", w, phi, phi)
         d = np.linalg.solve(H, G[..., None])[..., 0]
         conv = np.abs(G).max(1) <= tol
         step = np.ones(ux.size)
@@ -82,7 +88,7 @@ def equilibrium_weights(ux, uy, T, tol=1e-12):
         lam = np.where(done[:, None], lam, lam + step[:, None] * d)
         done |= conv
         if done.all():
-            return np.exp(-(lam @ PHI.T))
+            return np.exp(-(lam @ phi.T))
     raise RuntimeError("Newton did not converge")
 
 
@@ -165,13 +171,13 @@ def sensor_alpha(eps):
     return a
 
 
-def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k):
+def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k, constraints=8):
     """h_eq (1 + k phi_h) of eqs. (GradGeneral_f), (GradGeneral_g) in lattice
     (Lx, Ly) at absolute (rho, u, T); du = (d_x u_x, d_y u_x, d_x u_y,
     d_y u_y), dT = (d_x T, d_y T); mu = rho nu, kappa = rho Cp nu (unit
     Prandtl number)."""
     Cp = GAMMA * CV
-    w = equilibrium_weights(ux - Lx, uy - Ly, T)
+    w = equilibrium_weights(ux - Lx, uy - Ly, T, constraints=constraints)
     cx = CX[None, :] + Lx[:, None] - ux[:, None]
     cy = CY[None, :] + Ly[:, None] - uy[:, None]
     mu = rho * nu
@@ -208,15 +214,16 @@ def gradients(ux, uy, T, nx, ny):
 class AdaptiveGrid:
     """The adaptive model on a periodic nx x ny grid (row-major nodes)."""
 
-    def __init__(self, wl):
+    def __init__(self, wl, constraints=8):
         self.nu, self.hw, self.sensor = wl.nu, wl.halfwidth, wl.sensor
+        self.M = constraints
         self.nx, self.ny = wl.nx, wl.ny
         rho, ux, uy, T = (a.ravel().copy() for a in (wl.rho, wl.ux, wl.uy, wl.T))
         Lx = np.ceil(ux - 0.5).astype(int)
         Ly = np.ceil(uy - 0.5).astype(int)
         # Grad initial condition (Sec. IV.A.1, reading: pre-collision), then a collision
         du, dT = gradients(ux, uy, T, self.nx, self.ny)
-        f, g = grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, self.nu, 1.0)
+        f, g = grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, self.nu, 1.0, self.M)
         self.collide(f, g, Lx, Ly)
 
     def select(self, u, L):
@@ -228,7 +235,7 @@ class AdaptiveGrid:
         upx, upy = (f @ CX) / rho, (f @ CY) / rho
         T = (f @ SQ + g.sum(1) - rho * (upx * upx + upy * upy)) / (2 * rho * CV)
         ux, uy = upx + Lx, upy + Ly
-        feq = rho[:, None] * equilibrium_weights(upx, upy, T)
+        feq = rho[:, None] * equilibrium_weights(upx, upy, T, constraints=self.M)
         geq = (2 * CV - D) * T[:, None] * feq
         tau = 0.5 + self.nu / T
         if self.sensor:
@@ -257,7 +264,8 @@ class AdaptiveGrid:
             rho, ux, uy, T = (a[s] for a in self.mac)
             du, dT = gradients(*self.mac[1:], self.nx, self.ny)
             hf, hg = grad_pops(rho, ux, uy, T, [d[s] for d in du], [d[s] for d in dT],
-                               Lx[nodes], Ly[nodes], self.nu, 1.0 - 1.0 / (0.5 + self.nu / T))
+                               Lx[nodes], Ly[nodes], self.nu, 1.0 - 1.0 / (0.5 + self.nu / T),
+                               self.M)
             f[nodes, ks] = hf[np.arange(nodes.size), ks]
             g[nodes, ks] = hg[np.arange(nodes.size), ks]
         self.rebuilt = nodes.size
@@ -281,7 +289,11 @@ ADAPTIVE_CASES = {
     "riemann_table1_48": lambda steps: W.riemann_table1(48, steps=steps),
     "vortex_48": lambda steps: W.config2(48, steps),
 }
-ADAPTIVE_STEPS = {"four_quadrant_64": 20, "riemann_table1_48": 20, "vortex_48": 20}
+ADAPTIVE_STEPS = {"four_quadrant_64": 20, "riemann_table1_48": 20, "vortex_48": 20,
+                  "four_quadrant_64_four_constraints": 20}
+# the four-constraint set (next item f3, eq. feqNum_4Mom) on the same draw
+ADAPTIVE_CASES["four_quadrant_64_four_constraints"] = lambda steps: W.four_quadrant(64, steps)
+CONSTRAINTS = {"four_quadrant_64_four_constraints": 4}
 
 
 @pytest.mark.parametrize("case", list(ADAPTIVE_CASES))
@@ -290,12 +302,13 @@ def test_independent_adaptive_line_matches_the_oracle(case):
     node, select the same lattices and rebuild the same number of links."""
     steps = ADAPTIVE_STEPS.get(case, 40)
     wl = ADAPTIVE_CASES[case](steps)
-    line = AdaptiveGrid(wl)
+    M = CONSTRAINTS.get(case, 8)
+    line = AdaptiveGrid(wl, M)
     rebuilt = 0
     for _ in range(steps):
         line.step()
         rebuilt += line.rebuilt
-    s = oracle.Sim.from_workload(wl)
+    s = oracle.Sim.from_workload(wl, constraints=M)
     s.step(steps)
     m = {k: v.ravel() for k, v in s.macros().items()}
     rho, ux, uy, T = line.mac
