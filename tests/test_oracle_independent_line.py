@@ -171,7 +171,7 @@ def sensor_alpha(eps):
     return a
 
 
-def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k, constraints=8):
+def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k, constraints=8, pr=1.0, post_tau=None):
     """h_eq (1 + k phi_h) of eqs. (GradGeneral_f), (GradGeneral_g) in lattice
     (Lx, Ly) at absolute (rho, u, T); du = (d_x u_x, d_y u_x, d_x u_y,
     d_y u_y), dT = (d_x T, d_y T); mu = rho nu, kappa = rho Cp nu (unit
@@ -185,7 +185,7 @@ def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k, constraints=8):
     sxx = -mu * (2.0 * du[0] - (2.0 / D) * div)
     syy = -mu * (2.0 * du[3] - (2.0 / D) * div)
     sxy = -mu * (du[1] + du[2])
-    kappa = rho * Cp * nu
+    kappa = rho * Cp * nu / pr
     qc = -kappa[:, None] * (dT[0][:, None] * cx + dT[1][:, None] * cy)
     c2 = cx * cx + cy * cy
     r, t = rho[:, None], T[:, None]
@@ -195,7 +195,44 @@ def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k, constraints=8):
     feq = r * w
     geq = (2 * CV - D) * t * feq
     k = np.broadcast_to(np.asarray(k, dtype=np.float64), rho.shape)[:, None]
+    if pr != 1.0 and post_tau is not None:
+        # eq. (Shakhov) applied to the Grad populations (App. E): their heat
+        # flux in the receiver's frame, then each link's share of the term
+        fg, gg = feq * (1 + phif), geq * (1 + phig)
+        upx, upy = ux - Lx, uy - Ly
+        qx, qy = heat_flux(fg, gg, upx, upy)
+        sf, sg = shakhov_shapes(feq, upx, upy, rho, T, qx, qy)
+        tau = post_tau
+        ks = (1.0 / tau - 1.0 / (0.5 + (tau - 0.5) / pr))[:, None]
+        return feq + k * (fg - feq) + ks * feq * sf, geq + k * (gg - geq) + ks * geq * sg
     return feq * (1 + k * phif), geq * (1 + k * phig)
+
+
+def shakhov_shapes(feq, upx, upy, rho, T, qx, qy):
+    """Reading D-Pr of eq. (Shakhov): phi_S,f = q.cbar / (rho Cp T^2)
+    (|cbar|^2 / (2T) - (D + 2)/2), phi_S,g = q.cbar / (rho Cp T^2), cbar =
+    xi - u' in the lattice's frame, with f_eq phi_S,f made free of mass,
+    momentum and energy by removing its f_eq-weighted projection on (1,
+    cbar_x, cbar_y, |cbar|^2)."""
+    Cp = GAMMA * CV
+    cx = CX[None, :] - upx[:, None]
+    cy = CY[None, :] - upy[:, None]
+    c2 = cx * cx + cy * cy
+    a = (qx[:, None] * cx + qy[:, None] * cy) / (rho * Cp * T * T)[:, None]
+    sf = a * (c2 / (2 * T[:, None]) - 0.5 * (D + 2))
+    e = np.stack([np.ones_like(cx), cx, cy, c2], 2)                 # n x 21 x 4
+    gram = np.einsum("ni,nij,nik->njk", feq, e, e)
+    r = np.einsum("ni,ni,nij->nj", feq, sf, e)
+    beta = np.linalg.solve(gram, r[..., None])[..., 0]
+    return sf - np.einsum("nij,nj->ni", e, beta), a
+
+
+def heat_flux(f, g, upx, upy):
+    """q = (1/2) sum_i cbar_i (|cbar_i|^2 f_i + g_i), cbar = xi - u'."""
+    cx = CX[None, :] - upx[:, None]
+    cy = CY[None, :] - upy[:, None]
+    h = (cx * cx + cy * cy) * f + g
+    return 0.5 * (cx * h).sum(1), 0.5 * (cy * h).sum(1)
 
 
 def central(a, nx, ny):
@@ -214,8 +251,8 @@ def gradients(ux, uy, T, nx, ny):
 class AdaptiveGrid:
     """The adaptive model on a periodic nx x ny grid (row-major nodes)."""
 
-    def __init__(self, wl, constraints=8, shift_mode=None, halfwidth=None):
-        self.nu, self.sensor = wl.nu, wl.sensor
+    def __init__(self, wl, constraints=8, shift_mode=None, halfwidth=None, prandtl=1.0):
+        self.nu, self.sensor, self.pr = wl.nu, wl.sensor, prandtl
         self.hw = wl.halfwidth if halfwidth is None else halfwidth
         self.mode = wl.shift_mode if shift_mode is None else shift_mode
         self.M = constraints
@@ -232,7 +269,7 @@ class AdaptiveGrid:
             Ly = np.ceil(uy - 0.5).astype(int)
         # Grad initial condition (Sec. IV.A.1, reading: pre-collision), then a collision
         du, dT = gradients(ux, uy, T, self.nx, self.ny)
-        f, g = grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, self.nu, 1.0, self.M)
+        f, g = grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, self.nu, 1.0, self.M, self.pr)
         self.collide(f, g, Lx, Ly)
 
     def select(self, u, L):
@@ -282,8 +319,17 @@ class AdaptiveGrid:
         tau = 0.5 + self.nu / T
         if self.sensor:
             tau = tau * sensor_alpha(np.mean(np.abs(f - feq) / feq, axis=1))
-        self.f = f - (f - feq) / tau[:, None]
-        self.g = g - (g - geq) / tau[:, None]
+        f1 = f - (f - feq) / tau[:, None]
+        g1 = g - (g - geq) / tau[:, None]
+        if self.pr != 1.0:
+            # eq. (Shakhov): BGK plus (1/tau - 1/tau_Pr) h_eq phi_S, with q the
+            # heat flux of the populations being collided
+            qx, qy = heat_flux(f, g, upx, upy)
+            sf, sg = shakhov_shapes(feq, upx, upy, rho, T, qx, qy)
+            ks = (1.0 / tau - 1.0 / (0.5 + (tau - 0.5) / self.pr))[:, None]
+            f1 = f1 + ks * feq * sf
+            g1 = g1 + ks * geq * sg
+        self.f, self.g = f1, g1
         self.mac = (rho, ux, uy, T)
         self.Uc = (Lx, Ly)
         self.Un = self.select_next(ux, uy, Lx, Ly)
@@ -307,7 +353,7 @@ class AdaptiveGrid:
             du, dT = gradients(*self.mac[1:], self.nx, self.ny)
             hf, hg = grad_pops(rho, ux, uy, T, [d[s] for d in du], [d[s] for d in dT],
                                Lx[nodes], Ly[nodes], self.nu, 1.0 - 1.0 / (0.5 + self.nu / T),
-                               self.M)
+                               self.M, self.pr, post_tau=0.5 + self.nu / T)
             f[nodes, ks] = hf[np.arange(nodes.size), ks]
             g[nodes, ks] = hg[np.arange(nodes.size), ks]
         self.rebuilt = nodes.size
@@ -345,6 +391,13 @@ ADAPTIVE_STEPS["sod_static_shift"] = 32
 ADAPTIVE_CASES["four_quadrant_64_neighbourhood"] = lambda steps: W.four_quadrant(64, steps)
 ADAPTIVE_STEPS["four_quadrant_64_neighbourhood"] = 20
 OPTIONS = {"four_quadrant_64_neighbourhood": dict(shift_mode=3, halfwidth=0.9)}
+# the flexible-Prandtl collision (next item f4, reading D-Pr) at Pr = 0.71 on the
+# quadrant draw and on the advected Sod line
+ADAPTIVE_CASES["four_quadrant_64_prandtl"] = lambda steps: W.four_quadrant(64, steps)
+ADAPTIVE_STEPS["four_quadrant_64_prandtl"] = 20
+OPTIONS["four_quadrant_64_prandtl"] = dict(prandtl=0.71)
+ADAPTIVE_CASES["advected_sod_prandtl"] = ADAPTIVE_CASES["advected_sod_sensor"]
+OPTIONS["advected_sod_prandtl"] = dict(prandtl=0.71)
 
 
 @pytest.mark.parametrize("case", list(ADAPTIVE_CASES))
@@ -373,3 +426,7 @@ def test_independent_adaptive_line_matches_the_oracle(case):
     assert rebuilt == s.stats()["mismatched_links"] > 20 * steps
     assert np.array_equal(line.Uc[0], m["Ucx"]) and np.array_equal(line.Uc[1], m["Ucy"])
     assert max(err.values()) <= 1e-10, err
+    if "prandtl" in opts:   # the term moves these fields well beyond the agreement
+        b = oracle.Sim.from_workload(wl, constraints=M)
+        b.step(steps)
+        assert np.abs(b.macros()["T"].ravel() - m["T"]).max() > 1e-6
