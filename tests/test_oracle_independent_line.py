@@ -3,7 +3,8 @@ a vectorised numpy D2Q21 DDF-BGK on periodic grids, written here from the
 paper's definitions and sharing no code with the oracle.  First on the
 shear wave in one lattice (Sec. IV.B.1), then with lattices that follow the
 flow, rebuilt links and the sensor (a1-a6 of the step) on lines and on
-small 2D grids.
+small 2D grids, with every constraint set (8 and 4 on D2Q21, 13 on
+D2Q49), shift mode and the flexible-Prandtl collision.
 
 What differs from the oracle: the populations are held node x velocity and
 streamed with np.roll (in the one-lattice case in the frame of the lattice,
@@ -38,6 +39,15 @@ CX = np.array([0.0] + [s * p[0] for p in PAIRS for s in (1, -1)])
 CY = np.array([0.0] + [s * p[1] for p in PAIRS for s in (1, -1)])
 SQ = CX * CX + CY * CY
 PHI = np.stack([np.ones(21), CX, CY, CX * CX, CX * CY, CY * CY, CX * SQ, CY * SQ], 1)
+# the reference model's lattice (App. C): D2Q49 = {0, +-1, +-2, +-3}^2
+CX49 = np.array([float(x) for y in range(-3, 4) for x in range(-3, 4)])
+CY49 = np.array([float(y) for y in range(-3, 4) for x in range(-3, 4)])
+
+
+def lattice(Q):
+    """(c_x, c_y, |c|^2) of D2Q21 or D2Q49."""
+    cx, cy = (CX, CY) if Q == 21 else (CX49, CY49)
+    return cx, cy, cx * cx + cy * cy
 GAMMA = 1.4
 CV = 1.0 / (GAMMA - 1.0)   # per unit mass, R = 1
 D = 2
@@ -60,6 +70,19 @@ def equilibrium_weights(ux, uy, T, tol=1e-12, constraints=8):
     if constraints == 8:
         phi, m = PHI, maxwellian_targets(ux, uy, T)
         lam = np.zeros((ux.size, 8))
+        lam[:, 3] = lam[:, 5] = 0.5 / T
+    elif constraints == 13:
+        # eqs. (G0)-(G4yyaa) on D2Q49: moments up to the third order and the
+        # contracted fourth ones, E = |u|^2 / 2 + T
+        cx, cy, sq = lattice(49)
+        phi = np.stack([np.ones(49), cx, cy, cx * cx, cx * cy, cy * cy, cx ** 3, cx * cx * cy,
+                        cx * cy * cy, cy ** 3, cx * cx * sq, cx * cy * sq, cy * cy * sq], 1)
+        E = 0.5 * (ux * ux + uy * uy) + T
+        m = np.stack([np.ones_like(ux), ux, uy, ux * ux + T, ux * uy, uy * uy + T,
+                      ux * (ux * ux + 3 * T), (ux * ux + T) * uy, ux * (uy * uy + T),
+                      uy * (uy * uy + 3 * T), 2 * ((E + 2 * T) * ux * ux + (E + T) * T),
+                      2 * (E + 2 * T) * ux * uy, 2 * ((E + 2 * T) * uy * uy + (E + T) * T)], 1)
+        lam = np.zeros((ux.size, 13))
         lam[:, 3] = lam[:, 5] = 0.5 / T
     else:  # mass, momentum and energy only (eq. feqNum_4Mom)
         phi = np.stack([np.ones(21), CX, CY, SQ], 1)
@@ -178,8 +201,9 @@ def grad_pops(rho, ux, uy, T, du, dT, Lx, Ly, nu, k, constraints=8, pr=1.0, post
     Prandtl number)."""
     Cp = GAMMA * CV
     w = equilibrium_weights(ux - Lx, uy - Ly, T, constraints=constraints)
-    cx = CX[None, :] + Lx[:, None] - ux[:, None]
-    cy = CY[None, :] + Ly[:, None] - uy[:, None]
+    CXq, CYq, _ = lattice(w.shape[1])
+    cx = CXq[None, :] + Lx[:, None] - ux[:, None]
+    cy = CYq[None, :] + Ly[:, None] - uy[:, None]
     mu = rho * nu
     div = du[0] + du[3]
     sxx = -mu * (2.0 * du[0] - (2.0 / D) * div)
@@ -215,8 +239,9 @@ def shakhov_shapes(feq, upx, upy, rho, T, qx, qy):
     momentum and energy by removing its f_eq-weighted projection on (1,
     cbar_x, cbar_y, |cbar|^2)."""
     Cp = GAMMA * CV
-    cx = CX[None, :] - upx[:, None]
-    cy = CY[None, :] - upy[:, None]
+    CXq, CYq, _ = lattice(feq.shape[1])
+    cx = CXq[None, :] - upx[:, None]
+    cy = CYq[None, :] - upy[:, None]
     c2 = cx * cx + cy * cy
     a = (qx[:, None] * cx + qy[:, None] * cy) / (rho * Cp * T * T)[:, None]
     sf = a * (c2 / (2 * T[:, None]) - 0.5 * (D + 2))
@@ -229,8 +254,9 @@ def shakhov_shapes(feq, upx, upy, rho, T, qx, qy):
 
 def heat_flux(f, g, upx, upy):
     """q = (1/2) sum_i cbar_i (|cbar_i|^2 f_i + g_i), cbar = xi - u'."""
-    cx = CX[None, :] - upx[:, None]
-    cy = CY[None, :] - upy[:, None]
+    CXq, CYq, _ = lattice(f.shape[1])
+    cx = CXq[None, :] - upx[:, None]
+    cy = CYq[None, :] - upy[:, None]
     h = (cx * cx + cy * cy) * f + g
     return 0.5 * (cx * h).sum(1), 0.5 * (cy * h).sum(1)
 
@@ -310,9 +336,10 @@ class AdaptiveGrid:
         return bx, by
 
     def collide(self, f, g, Lx, Ly):
+        cxq, cyq, sqq = lattice(f.shape[1])
         rho = f.sum(1)
-        upx, upy = (f @ CX) / rho, (f @ CY) / rho
-        T = (f @ SQ + g.sum(1) - rho * (upx * upx + upy * upy)) / (2 * rho * CV)
+        upx, upy = (f @ cxq) / rho, (f @ cyq) / rho
+        T = (f @ sqq + g.sum(1) - rho * (upx * upx + upy * upy)) / (2 * rho * CV)
         ux, uy = upx + Lx, upy + Ly
         feq = rho[:, None] * equilibrium_weights(upx, upy, T, constraints=self.M)
         geq = (2 * CV - D) * T[:, None] * feq
@@ -339,11 +366,12 @@ class AdaptiveGrid:
         Lx, Ly = self.Un
         n = np.arange(self.nx * self.ny)
         x, y = n % self.nx, n // self.nx
-        sx = (x[:, None] - (CX.astype(int)[None, :] + Lx[:, None])) % self.nx
-        sy = (y[:, None] - (CY.astype(int)[None, :] + Ly[:, None])) % self.ny
+        cxq, cyq, _ = lattice(self.f.shape[1])
+        sx = (x[:, None] - (cxq.astype(int)[None, :] + Lx[:, None])) % self.nx
+        sy = (y[:, None] - (cyq.astype(int)[None, :] + Ly[:, None])) % self.ny
         src = sy * self.nx + sx                                   # node x plane
         same = (self.Uc[0][src] == Lx[:, None]) & (self.Uc[1][src] == Ly[:, None])
-        planes = np.arange(21)[None, :]
+        planes = np.arange(cxq.size)[None, :]
         f = np.where(same, self.f[src, planes], 0.0)
         g = np.where(same, self.g[src, planes], 0.0)
         nodes, ks = np.nonzero(~same)
@@ -398,6 +426,11 @@ ADAPTIVE_STEPS["four_quadrant_64_prandtl"] = 20
 OPTIONS["four_quadrant_64_prandtl"] = dict(prandtl=0.71)
 ADAPTIVE_CASES["advected_sod_prandtl"] = ADAPTIVE_CASES["advected_sod_sensor"]
 OPTIONS["advected_sod_prandtl"] = dict(prandtl=0.71)
+# the reference model (next item f3): D2Q49 with 13 constraints on the
+# quadrant draw at 32^2
+ADAPTIVE_CASES["four_quadrant_32_reference_model"] = lambda steps: W.four_quadrant(32, steps)
+ADAPTIVE_STEPS["four_quadrant_32_reference_model"] = 10
+CONSTRAINTS["four_quadrant_32_reference_model"] = 13
 
 
 @pytest.mark.parametrize("case", list(ADAPTIVE_CASES))
